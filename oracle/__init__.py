@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for the exact discrete Poisson solver on spherical polar grids.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call anything in this
+package.  The product library (``paper_1806_06623_amd``) never routes through
+it, and the two share no code: the only module both sides use is the seeded
+input generator package ``synthetic``, which holds none of the method's
+arithmetic.
+
+What it computes (Mueller & Chan 2019, "An FFT-based solution method for the
+Poisson equation on 3D spherical polar grids"):
+
+* ``geometry``   -- Sec. 3.1: cell volumes, interface areas, the factored
+                    operator coefficients R_i and S_j.
+* ``spectral``   -- Sec. 3.2: FFT in phi, per-m theta eigensystems, forward
+                    projection, radial tridiagonal solves with the asymptotic
+                    outer boundary condition, inverse projection, inverse FFT.
+* ``dense``      -- the same discrete operator L assembled directly from the
+                    flux form of Sec. 3.1 as a dense matrix (tiny grids only),
+                    used to pin ``spectral`` independently.
+* ``laplacian``  -- L applied to a field by the local stencil plus the outer
+                    boundary term, for residuals and backward errors.
+* ``analytic``   -- closed forms used as pins (uniform sphere, the l=0
+                    cumulative-mass recurrence).
+
+Everything is float64 numpy; scipy supplies the symmetric tridiagonal
+eigensolver and numpy the real FFT (library primitives used as single steps).
+"""

@@ -1,0 +1,79 @@
+"""Apply the discrete operator L to a field, and residual diagnostics.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+L Phi is evaluated with the local stencil of Sec. 3.1 (radial, theta and phi
+fluxes between neighbouring cells, divided by the cell volume).  On the
+outermost shell the outward radial flux is the boundary term of Sec. 3.2,
+-beta(lambda_Omega) f_N per angular eigenmode; it is evaluated by
+transforming that one shell with the FFT and the theta eigenvectors of the
+spectral oracle, multiplying each mode by beta, and transforming back.
+"""
+import numpy as np
+
+from .geometry import grid_geometry
+from .spectral import outer_beta, theta_eigensystem
+
+
+def outer_flux(geom, shell):
+    """Outer-face term beta(A) Phi_shell for one (nth, nphi) shell."""
+    nphi = geom["nphi"]
+    c = np.fft.rfft(shell, axis=1) / nphi
+    out = np.empty_like(c)
+    for m in range(c.shape[1]):
+        lam, H = theta_eigensystem(geom, m)
+        coef = (H.T * geom["dmu"][None, :]) @ c[:, m]
+        out[:, m] = H @ (outer_beta(geom, lam) * coef)
+    return np.fft.irfft(out, n=nphi, axis=1) * nphi
+
+
+def apply(r_if, th_if, nphi, Phi, with_terms=False):
+    """L Phi (and, if asked, the absolute stencil terms for backward errors).
+
+    With ``with_terms`` the second return value is |L| |Phi| evaluated term
+    by term (each flux contribution in absolute value), the denominator of
+    the componentwise backward error.
+    """
+    g = grid_geometry(r_if, th_if, nphi)
+    P = np.asarray(Phi, dtype=np.float64)
+    nr = g["nr"]
+    V, R, S, al, sig, dmu = g["V"], g["R"], g["S"], g["alpha"], g["sigma"], g["dmu"]
+    out = np.zeros_like(P)
+    mag = np.zeros_like(P)
+
+    # radial fluxes through interior faces i+1/2 (i = 0..nr-2)
+    fr = al[:, None, None] * (P[1:] - P[:-1])
+    ar = al[:, None, None] * (np.abs(P[1:]) + np.abs(P[:-1]))
+    out[:-1] += fr / V[:-1, None, None]
+    out[1:] -= fr / V[1:, None, None]
+    mag[:-1] += ar / V[:-1, None, None]
+    mag[1:] += ar / V[1:, None, None]
+    # outer face: -beta(A) Phi_N
+    fo = outer_flux(g, P[-1])
+    out[-1] -= fo / V[-1]
+    mag[-1] += np.abs(fo) / V[-1]
+
+    # theta fluxes through interior faces j+1/2, times R_i / dmu_j
+    ft = sig[1:-1][None, :, None] * (P[:, 1:] - P[:, :-1])
+    at = sig[1:-1][None, :, None] * (np.abs(P[:, 1:]) + np.abs(P[:, :-1]))
+    wt = R[:, None, None]
+    out[:, :-1] += wt * ft / dmu[None, :-1, None]
+    out[:, 1:] -= wt * ft / dmu[None, 1:, None]
+    mag[:, :-1] += wt * at / dmu[None, :-1, None]
+    mag[:, 1:] += wt * at / dmu[None, 1:, None]
+
+    # phi second difference, times R_i S_j / dphi^2
+    wp = (R[:, None] * S[None, :] / g["dphi"] ** 2)[:, :, None]
+    Pp, Pm = np.roll(P, -1, axis=2), np.roll(P, 1, axis=2)
+    out += wp * (Pp - 2.0 * P + Pm)
+    mag += wp * (np.abs(Pp) + 2.0 * np.abs(P) + np.abs(Pm))
+    if with_terms:
+        return out, mag
+    return out
+
+
+def backward_error(r_if, th_if, nphi, Phi, rho, G=1.0):
+    """Componentwise backward error max |s - L Phi| / (|L||Phi| + |s|)."""
+    s = 4.0 * np.pi * G * np.asarray(rho, dtype=np.float64)
+    LP, mag = apply(r_if, th_if, nphi, Phi, with_terms=True)
+    return float(np.max(np.abs(s - LP) / (mag + np.abs(s))))

@@ -1,0 +1,242 @@
+"""Pins of the FP64 oracle to facts the paper and the mathematics fix.
+
+None of these checks re-types the oracle's own formulas: each compares it with
+something independent (a closed form, a worked example the paper prints, a
+dense direct solve of the operator assembled from the flux form, an invariant
+of the exact discrete problem).  ``test_planted_mistakes_are_caught`` shows
+that plausible slips in the oracle fail at least one of them.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import analytic, dense, geometry, laplacian, spectral
+import synthetic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def random_r_if(rng, nr, r0=0.0):
+    return np.concatenate(([r0], r0 + np.cumsum(rng.uniform(0.4, 1.6, nr))))
+
+
+def random_th_if(rng, nth):
+    inner = np.sort(rng.uniform(0.15, np.pi - 0.15, nth - 1))
+    return np.concatenate(([0.0], inner, [np.pi]))
+
+
+# ---------------------------------------------------------------- geometry
+def test_worked_example_cell_centres():
+    """Sec. 5.1: zone (j, k) = (32, 128) of 128 x 256 sits at (0.246 pi, 0.996 pi)."""
+    with open(os.path.join(GOLDEN, "point_source_zone.json")) as fh:
+        g = json.load(fh)
+    _, th, phi = geometry.cell_centres([0.0, 1.0], synthetic.theta_interfaces(g["nth"]), g["nphi"])
+    assert round(th[g["j_one_based"] - 1] / np.pi, 3) == g["theta_over_pi"]
+    assert round(phi[g["k_one_based"] - 1] / np.pi, 3) == g["phi_over_pi"]
+
+
+def test_volumes_sum_to_ball():
+    """Sum of delta V over all cells is the ball volume 4/3 pi r_out^3."""
+    rng = np.random.default_rng(1)
+    r_if = random_r_if(rng, 17)
+    th_if = random_th_if(rng, 9)
+    vol = geometry.cell_volumes(r_if, th_if, 12).sum() * 12
+    assert abs(vol / (4.0 / 3.0 * np.pi * r_if[-1] ** 3) - 1.0) < 1e-14
+
+
+def test_factored_coefficients_continuum_limits():
+    """R_i -> 1/r_i^2 and S_j -> 1/sin^2 theta_j at second order in the spacing."""
+    errs_r, errs_s = [], []
+    for n in (64, 128, 256):
+        g = geometry.grid_geometry(synthetic.uniform_interfaces(n, 1.0, 2.0),
+                                   synthetic.theta_interfaces(n), 8)
+        errs_r.append(np.max(np.abs(g["R"] * g["r"] ** 2 - 1.0)))
+        errs_s.append(np.max(np.abs(g["S"] * np.sin(g["th"]) ** 2 - 1.0)[n // 4: 3 * n // 4]))
+    for e in (errs_r, errs_s):
+        assert 3.5 < e[0] / e[1] < 4.5 and 3.5 < e[1] / e[2] < 4.5
+
+
+# ------------------------------------------------------------ eigensystems
+def test_phi_eigenvalues_match_circulant_spectrum():
+    """lambda_{phi,m} are the eigenvalues of the periodic second difference / dphi^2."""
+    for n in (6, 7, 16):
+        dphi = 2 * np.pi / n
+        C = (np.roll(np.eye(n), 1, 1) + np.roll(np.eye(n), -1, 1) - 2 * np.eye(n)) / dphi ** 2
+        ev = np.sort(np.linalg.eigvalsh(C))
+        lam = spectral.phi_eigenvalues(n)
+        full = np.concatenate((lam, lam[1:(n + 1) // 2]))     # m and N - m
+        assert np.allclose(np.sort(full), ev, rtol=0, atol=1e-12 * np.abs(ev).max())
+
+
+@pytest.mark.parametrize("m", [0, 1, 5, 40, 128])
+def test_theta_eigensystem_orthonormal_and_exact(m):
+    """H^T D H = I and K H = D H Lambda to rounding, for uniform 128-zone theta."""
+    g = geometry.grid_geometry([0.0, 1.0], synthetic.theta_interfaces(128), 256)
+    lam, H = spectral.theta_eigensystem(g, m)
+    D = g["dmu"]
+    assert np.max(np.abs(H.T @ (D[:, None] * H) - np.eye(128))) < 1e-13
+    # K assembled here from the flux form on the unit sphere, not from the oracle
+    A, omega = dense.shell_angular_operator(synthetic.theta_interfaces(128), 256)
+    # restrict A to the m-th Fourier mode: apply to H_l(j) cos(m phi_k)
+    phi = (np.arange(256) + 0.5) * 2 * np.pi / 256
+    for l in (0, 7, 127):
+        v = np.outer(H[:, l], np.cos(m * phi)).reshape(-1)
+        Av = A @ v
+        assert np.max(np.abs(Av - lam[l] * v)) < 1e-10 * np.max(np.abs(lam))
+
+
+def test_theta_eigenvalues_continuum_limit():
+    """lambda_Omega -> -(m + k)(m + k + 1) (Y_lm eigenvalues) at second order."""
+    errs = []
+    for n in (32, 64, 128):
+        g = geometry.grid_geometry([0.0, 1.0], synthetic.theta_interfaces(n), 2 * n)
+        e = []
+        for m in (0, 1, 3):
+            lam = np.sort(spectral.theta_eigensystem(g, m)[0])[::-1]
+            exact = np.array([-(m + k) * (m + k + 1) for k in range(4)])
+            if m == 0:
+                assert abs(lam[0]) < 1e-11 * abs(lam).max()   # constant mode, exactly 0
+                lam, exact = lam[1:4], exact[1:4]
+            else:
+                lam, exact = lam[:4], exact
+            e.append(np.max(np.abs(lam / exact - 1.0)))
+        errs.append(max(e))
+    assert errs[-1] < 2e-3
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+
+
+# ------------------------------------------------------ whole-method pins
+CASES = [
+    # (nr, nth, nphi, r0, uniform_theta)
+    (5, 4, 6, 0.0, True),
+    (6, 6, 8, 0.0, True),
+    (4, 5, 5, 0.7, False),
+    (7, 3, 4, 0.0, False),
+    (3, 6, 7, 2.0, True),
+]
+
+
+@pytest.mark.parametrize("nr,nth,nphi,r0,uni", CASES)
+def test_spectral_matches_dense_brute_force(nr, nth, nphi, r0, uni):
+    """The spectral method reaches the unique solution of the dense system."""
+    rng = np.random.default_rng(nr * 100 + nth * 10 + nphi)
+    r_if = random_r_if(rng, nr, r0)
+    th_if = synthetic.theta_interfaces(nth) if uni else random_th_if(rng, nth)
+    rho = rng.standard_normal((nr, nth, nphi))
+    ref = dense.solve(r_if, th_if, nphi, rho)
+    got = spectral.solve(r_if, th_if, nphi, rho)
+    assert rel(got, ref) < 1e-13
+
+
+def test_dense_operator_is_volume_symmetric():
+    """delta V * L is symmetric: the flux form is self-adjoint (reciprocity)."""
+    rng = np.random.default_rng(7)
+    r_if, th_if, nphi = random_r_if(rng, 4), random_th_if(rng, 4), 5
+    L = dense.assemble(r_if, th_if, nphi)
+    dV = np.repeat(geometry.cell_volumes(r_if, th_if, nphi).reshape(-1), nphi)
+    S = dV[:, None] * L
+    assert np.max(np.abs(S - S.T)) < 1e-13 * np.max(np.abs(S))
+
+
+def test_reciprocity_of_spectral_solutions():
+    """Phi of a unit mass at b, read at a, equals Phi of a unit mass at a, read at b."""
+    rng = np.random.default_rng(11)
+    r_if, th_if, nphi = random_r_if(rng, 8), synthetic.theta_interfaces(6), 8
+    dV = geometry.cell_volumes(r_if, th_if, nphi)
+    plan = spectral.Plan(r_if, th_if, nphi)
+    a, b = (1, 2, 3), (6, 4, 0)
+    ra = np.zeros((8, 6, nphi)); ra[a] = 1.0 / dV[a[:2]]
+    rb = np.zeros((8, 6, nphi)); rb[b] = 1.0 / dV[b[:2]]
+    pa, pb = plan.solve(ra), plan.solve(rb)
+    assert abs(pa[b] - pb[a]) < 1e-13 * abs(pa[b])
+
+
+def test_spherical_source_closed_form():
+    """A spherically symmetric source excites only l = m = 0: discrete Gauss's law."""
+    r_if = synthetic.stellar_r_interfaces(128)
+    th_if = synthetic.theta_interfaces(16)
+    nphi = 16
+    r = 0.5 * (r_if[:-1] + r_if[1:])
+    rho_r = (1 + (r / 20.0) ** 2) ** -1.5
+    rho = np.broadcast_to(rho_r[:, None, None], (128, 16, nphi)).copy()
+    phi = spectral.solve(r_if, th_if, nphi, rho)
+    f = analytic.spherical_discrete_potential(r_if, 4 * np.pi * rho_r)
+    assert rel(phi, np.broadcast_to(f[:, None, None], phi.shape)) < 1e-13
+    spread = np.max(phi.max(axis=(1, 2)) - phi.min(axis=(1, 2)))
+    assert spread < 1e-13 * np.max(np.abs(phi))
+
+
+def test_uniform_sphere_second_order():
+    """Homogeneous sphere: the discrete solution converges to the Newtonian
+    potential at second order in the radial spacing."""
+    errs = []
+    for nr in (32, 64, 128):
+        r_if = synthetic.uniform_interfaces(nr, 0.0, 1.0)
+        th_if = synthetic.theta_interfaces(8)
+        r = 0.5 * (r_if[:-1] + r_if[1:])
+        rho = np.broadcast_to((r < 0.5)[:, None, None].astype(float), (nr, 8, 8)).copy()
+        phi = spectral.solve(r_if, th_if, 8, rho)
+        ex = analytic.uniform_sphere_potential(r, 0.5)
+        errs.append(np.max(np.abs(phi[:, 0, 0] - ex)) / np.max(np.abs(ex)))
+    assert errs[0] < 1e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_componentwise_backward_error_at_roundoff():
+    """|s - L Phi| is at rounding level of |L||Phi| + |s| on a stellar grid."""
+    c = synthetic.stellar_case(nr=96, nth=32, nphi=32, seed=5)
+    phi = spectral.solve(c["r_if"], c["th_if"], c["nphi"], c["rho"])
+    eta = laplacian.backward_error(c["r_if"], c["th_if"], c["nphi"], phi, c["rho"])
+    assert eta < 1e-14
+
+
+def test_shift_and_reflection_equivariance():
+    """Rolling rho in phi rolls Phi; mirroring rho in theta mirrors Phi."""
+    rng = np.random.default_rng(3)
+    r_if, th_if, nphi = random_r_if(rng, 12), synthetic.theta_interfaces(10), 12
+    rho = rng.standard_normal((12, 10, nphi))
+    plan = spectral.Plan(r_if, th_if, nphi)
+    phi = plan.solve(rho)
+    assert rel(plan.solve(np.roll(rho, 3, axis=2)), np.roll(phi, 3, axis=2)) < 1e-13
+    assert rel(plan.solve(rho[:, ::-1, :]), phi[:, ::-1, :]) < 1e-12
+
+
+# --------------------------------------------------- sensitivity of the pins
+def _pins_pass():
+    rng = np.random.default_rng(123)
+    r_if, th_if, nphi = random_r_if(rng, 5), random_th_if(rng, 4), 6
+    rho = rng.standard_normal((5, 4, nphi))
+    with np.errstate(invalid="ignore"):
+        try:
+            got = spectral.solve(r_if, th_if, nphi, rho)
+        except ValueError:        # a slip that produces NaN is caught too
+            return False
+    return rel(got, dense.solve(r_if, th_if, nphi, rho)) < 1e-13
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """Each plausible slip in the oracle breaks the dense-solve pin."""
+    assert _pins_pass()
+    orig_beta, orig_phi = spectral.outer_beta, spectral.phi_eigenvalues
+    orig_op, orig_geom = spectral.theta_operator, spectral.grid_geometry
+
+    slips = {
+        "lambda_phi sign dropped": ("phi_eigenvalues", lambda n: -orig_phi(n)),
+        "outer exponent dropped": ("outer_beta", lambda g, lam: orig_beta(g, lam) * (g["r_if"][-1] / g["r"][-1]) ** (
+            0.5 * (1 + np.sqrt(1 - 4 * np.asarray(lam))))),
+        "outer face at cell centre": ("outer_beta", lambda g, lam: orig_beta(g, lam) * g["r"][-1] / g["r_if"][-1]),
+        "1/dmu dropped in theta operator": ("theta_operator", lambda g, lp: (
+            orig_op(g, lp)[0] / g["dmu"], orig_op(g, lp)[1])),
+        "R_i taken as 1/r_i^2": ("grid_geometry", lambda *a: dict(orig_geom(*a), R=1.0 / orig_geom(*a)["r"] ** 2)),
+    }
+    for name, (attr, fn) in slips.items():
+        monkeypatch.setattr(spectral, attr, fn)
+        assert not _pins_pass(), name
+        monkeypatch.undo()
+    assert _pins_pass()
