@@ -1,0 +1,158 @@
+/*
+ * sphpoisson.h -- C ABI of the MI355X (gfx950) exact discrete Poisson solver
+ * on N_r x N_theta x N_phi spherical polar finite-volume grids.
+ *
+ * The method (Mueller & Chan 2019, "An FFT-based solution method for the
+ * Poisson equation on 3D spherical polar grids", Sec. 3):
+ *   s = 4 pi G rho                                    (Sec. 3.1)
+ *   real FFT of s along the uniform phi direction     (Sec. 3.2)
+ *   per azimuthal mode m: projection onto the eigenvectors of the discrete
+ *     theta operator hat-Delta_theta + S_j lambda_{phi,m}   (Sec. 3.2)
+ *   per (m, l): tridiagonal radial solve of Delta_r f + R_i lambda_Omega f
+ *     = s^ with the asymptotic outer boundary condition     (Sec. 3.2)
+ *   inverse projection and inverse FFT                      (Sec. 3.2)
+ * The discrete operator is the finite-volume Laplacian of Sec. 3.1 with
+ * zero-area pole faces, periodic phi, zero flux through the inner radial
+ * face (zero area when r_{1/2} = 0) and the outer condition above; the solver
+ * returns its unique solution.
+ *
+ * Conventions shared by every call:
+ *   - every function returns spp_status; on a non-OK status a message is
+ *     available from spp_last_error() (thread-local, valid until the next
+ *     call on the same thread);
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory of the current device; the library allocates no device
+ *     memory at all: the caller provides the plan buffer and the workspace;
+ *   - streams are hipStream_t passed as void*; NULL means the null stream.
+ *     Device work is only enqueued; the caller synchronises the stream;
+ *   - rho and Phi are row-major float64 arrays [N_r][N_theta][N_phi]
+ *     (phi fastest), i.e. a contiguous float64 tensor of shape
+ *     (N_r, N_theta, N_phi). Indices are 0-based (the paper's are 1-based).
+ */
+#ifndef SPHPOISSON_H
+#define SPHPOISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPP_OK = 0,
+    SPP_EINVAL = -1,     /* invalid argument (sizes, interfaces, NULL pointers) */
+    SPP_ENOTSUP = -2,    /* valid for the method, not supported by this build   */
+    SPP_EDEVICE = -3,    /* a HIP call failed                                   */
+    SPP_ENOMEM = -4,     /* host allocation failed                              */
+    SPP_ESTATE = -5,     /* object used out of order (e.g. solve before upload) */
+    SPP_ENONFINITE = -6  /* non-finite value detected                           */
+} spp_status;
+
+typedef enum {
+    SPP_FP64 = 0,          /* all stages in float64                                */
+    SPP_MIXED_FP32 = 1,    /* theta projections as FP32 MFMA products, FP32 spectral
+                              storage; FP64 radial solves and FP64 residual
+                              refinement (reserved: returns SPP_ENOTSUP until built) */
+    SPP_MIXED_BF16X3 = 2   /* split-BF16 (hi*hi + hi*lo + lo*hi) projections; as
+                              above (reserved)                                      */
+} spp_precision;
+
+typedef struct spp_grid_s* spp_grid;   /* host geometry, immutable        */
+typedef struct spp_plan_s* spp_plan;   /* eigensystems + device layout    */
+
+/*
+ * Create a grid from cell interfaces (Sec. 3.1: r_{i+-1/2}, theta_{j+-1/2},
+ * and a uniform phi spacing 2 pi / N_phi).
+ *   nr     >= 2 radial cells; r_if (host, nr+1 doubles) strictly increasing,
+ *          r_if[0] >= 0;
+ *   nth    >= 2 theta cells; th_if (host, nth+1 doubles) strictly increasing
+ *          from 0 to pi (checked to 1e-12, then snapped to exactly 0 and pi);
+ *          the cells need not be uniform (the separation of variables does not
+ *          require it, Sec. 3.1);
+ *   nphi   uniform phi cells; the GPU path needs a power of two in [4, 2048]
+ *          (SPP_ENOTSUP otherwise).
+ * The interface arrays are copied. *out receives the new grid.
+ * Errors: SPP_EINVAL for the conditions above or NULL pointers.
+ */
+spp_status spp_grid_create(int nr, const double* r_if, int nth, const double* th_if,
+                           int nphi, spp_grid* out);
+void spp_grid_destroy(spp_grid g);
+
+/*
+ * Set-up of Sec. 3.2, done once per grid on the host in float64: geometric
+ * factors (V_i, R_i, the face coefficients), lambda_{phi,m} for
+ * m = 0..N_phi/2, and for each m the eigenvalues lambda_{Omega,l,m} and the
+ * eigenvectors H_{l,m}(j) of the theta operator, orthonormal in the
+ * dmu-weighted inner product (so H^-1 = H^T diag(dmu)), by an implicit QL
+ * iteration on the symmetrised tridiagonal matrix.  Also the outer-boundary
+ * coefficients of every (l, m).  The grid may be destroyed afterwards.
+ * Errors: SPP_EINVAL (NULL), SPP_ENOMEM, SPP_ENOTSUP (nphi not a power of two
+ * in [4, 2048]), SPP_EDEVICE (eigen iteration failed to converge).
+ */
+spp_status spp_plan_create(spp_grid g, spp_plan* out);
+void spp_plan_destroy(spp_plan p);
+
+/*
+ * Device memory the caller must provide:
+ *   *plan_bytes       one buffer per plan, written by spp_plan_upload and
+ *                     read-only afterwards (eigenvector matrices, tables);
+ *   *workspace_bytes  scratch for one solve in flight; concurrent solves on
+ *                     different streams need separate workspaces.
+ * Both are multiples of 256 bytes; buffers must be 256-byte aligned.
+ */
+spp_status spp_plan_device_bytes(spp_plan p, size_t* plan_bytes, size_t* workspace_bytes);
+
+/*
+ * Copy the plan's tables into caller-owned device memory plan_dev (at least
+ * plan_bytes) on `stream`.  The host copy stays alive until the stream has
+ * executed the copy (the call synchronises the stream before returning).
+ * The plan remembers plan_dev; uploading again replaces it.
+ * Errors: SPP_EINVAL (NULL, misaligned), SPP_EDEVICE.
+ */
+spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream);
+
+/*
+ * Enqueue one FP64 solve Phi = L^-1 (4 pi G rho) on `stream` (Sec. 3.2):
+ *   rho_dev  device, [N_r][N_theta][N_phi] float64, read-only;
+ *   phi_dev  device, same shape, written (may not alias rho_dev);
+ *   G        the gravitational constant in the caller's units;
+ *   workspace_dev  device scratch of workspace_bytes (256-byte aligned).
+ * Errors (synchronous, nothing enqueued): SPP_EINVAL (NULL/misaligned/alias),
+ * SPP_ESTATE (plan not uploaded), SPP_EDEVICE (launch failure).
+ */
+spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double G,
+                     void* workspace_dev, void* stream);
+
+/*
+ * spp_solve with per-stage timing, for benchmarks and profiling.  Records
+ * HIP events on `stream` before the first and after each of the five stages
+ *   0 forward real FFT along phi (with s = 4 pi G rho)
+ *   1 forward theta projection (MFMA GEMM per Fourier component)
+ *   2 radial tridiagonal solves with the outer boundary condition
+ *   3 inverse theta projection (MFMA GEMM)
+ *   4 inverse real FFT along phi
+ * then waits for the last event and writes the stage durations in
+ * milliseconds to stage_ms (host, 5 doubles).  Blocks the calling thread.
+ * Errors: as spp_solve, plus SPP_EINVAL for stage_ms == NULL.
+ */
+spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev, double G,
+                              void* workspace_dev, void* stream, double* stage_ms);
+
+/*
+ * Host copy of the theta eigensystem of mode m (0 <= m <= N_phi/2), for tests:
+ *   H    host, N_theta*N_theta doubles, H[j*N_theta + l] = H_{l,m}(j);
+ *   lam  host, N_theta doubles, lambda_{Omega,l,m} in ascending order.
+ * Errors: SPP_EINVAL.
+ */
+spp_status spp_theta_eigensystem(spp_plan p, int m, double* H, double* lam);
+
+/* Grid sizes of a plan (any pointer may be NULL). */
+spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char* spp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHPOISSON_H */

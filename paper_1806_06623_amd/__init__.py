@@ -1,0 +1,17 @@
+"""MI355X-native exact discrete Poisson solver on spherical polar grids.
+
+Python binding of ``libsphpoisson.so`` (declared in ``include/sphpoisson.h``).
+The binding only marshals arguments: every step of a solve runs in the HIP
+kernels of the library.  PyTorch provides device memory and streams.
+Importing this package fails loudly if the library has not been built
+(``python paper_1806_06623_amd/build.py``).
+"""
+from ._binding import (  # noqa: F401
+    LIB_PATH,
+    Plan,
+    SphPoissonError,
+    lib,
+    precision_codes,
+)
+
+__all__ = ["Plan", "SphPoissonError", "lib", "LIB_PATH", "precision_codes"]

@@ -1,0 +1,153 @@
+"""ctypes binding of the C ABI in include/sphpoisson.h (argument marshalling only)."""
+import ctypes
+import os
+
+import numpy as np
+# torch first: it maps its own HIP runtime (libamdhip64.so.7), and the library
+# must bind to that same runtime instance.  Loading the library first would map
+# a second HIP/HSA runtime from /opt/rocm next to torch's, and device handles
+# (streams, memory) of one are unknown to the other.
+import torch  # noqa: F401
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsphpoisson.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_1806_06623_amd/build.py` "
+        "(there is no CPU fallback)")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+_c_int, _c_double, _c_size_t, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+lib.spp_grid_create.argtypes = [_c_int, _dp, _c_int, _dp, _c_int, ctypes.POINTER(_vp)]
+lib.spp_grid_create.restype = _c_int
+lib.spp_grid_destroy.argtypes = [_vp]
+lib.spp_grid_destroy.restype = None
+lib.spp_plan_create.argtypes = [_vp, ctypes.POINTER(_vp)]
+lib.spp_plan_create.restype = _c_int
+lib.spp_plan_destroy.argtypes = [_vp]
+lib.spp_plan_destroy.restype = None
+lib.spp_plan_device_bytes.argtypes = [_vp, ctypes.POINTER(_c_size_t), ctypes.POINTER(_c_size_t)]
+lib.spp_plan_device_bytes.restype = _c_int
+lib.spp_plan_upload.argtypes = [_vp, _vp, _vp]
+lib.spp_plan_upload.restype = _c_int
+lib.spp_solve.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp]
+lib.spp_solve.restype = _c_int
+lib.spp_solve_profiled.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp, _dp]
+lib.spp_solve_profiled.restype = _c_int
+lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
+lib.spp_theta_eigensystem.restype = _c_int
+lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
+lib.spp_plan_shape.restype = _c_int
+lib.spp_last_error.argtypes = []
+lib.spp_last_error.restype = ctypes.c_char_p
+
+precision_codes = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16x3": 2}
+
+
+class SphPoissonError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib.spp_last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != 0:
+        raise SphPoissonError(status, where)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Grid + set-up (host eigensolves) + device-resident tables.
+
+    ``Plan(r_if, th_if, nphi)`` creates the grid and the plan, allocates the
+    plan buffer and one workspace as torch uint8 tensors on ``device`` and
+    uploads the tables.  ``solve(rho)`` enqueues one solve on the current
+    torch stream and returns Phi (float64, same shape as rho).
+    """
+
+    def __init__(self, r_if, th_if, nphi, device="cuda"):
+        import torch
+        r_if, rp = _f64(r_if)
+        th_if, tp = _f64(th_if)
+        self.nr, self.nth, self.nphi = r_if.size - 1, th_if.size - 1, int(nphi)
+        grid = _vp()
+        _check(lib.spp_grid_create(self.nr, rp, self.nth, tp, self.nphi, ctypes.byref(grid)),
+               "spp_grid_create")
+        plan = _vp()
+        try:
+            _check(lib.spp_plan_create(grid, ctypes.byref(plan)), "spp_plan_create")
+        finally:
+            lib.spp_grid_destroy(grid)
+        self._plan = plan
+        pb, wb = _c_size_t(), _c_size_t()
+        _check(lib.spp_plan_device_bytes(plan, ctypes.byref(pb), ctypes.byref(wb)), "spp_plan_device_bytes")
+        self.plan_bytes, self.workspace_bytes = pb.value, wb.value
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        with torch.cuda.device(self.device):
+            self._plan_dev = torch.empty(self.plan_bytes, dtype=torch.uint8, device=self.device)
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            _check(lib.spp_plan_upload(plan, _vp(self._plan_dev.data_ptr()), _stream_ptr(None)),
+                   "spp_plan_upload")
+
+    @property
+    def shape(self):
+        return (self.nr, self.nth, self.nphi)
+
+    def new_workspace(self):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+
+    def solve(self, rho, G=1.0, out=None, workspace=None, stream=None):
+        import torch
+        if rho.dtype != torch.float64 or not rho.is_contiguous() or tuple(rho.shape) != self.shape:
+            raise ValueError(f"rho must be a contiguous float64 tensor of shape {self.shape}")
+        if rho.device != self.device:
+            raise ValueError("rho must live on the plan's device")
+        if out is None:
+            out = torch.empty_like(rho)
+        ws = self.workspace if workspace is None else workspace
+        _check(lib.spp_solve(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
+                             _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_solve")
+        return out
+
+    def solve_profiled(self, rho, out, G=1.0, stream=None):
+        """One solve with per-stage HIP-event timing; blocks until done.
+
+        Returns the five stage durations in ms (forward FFT, forward
+        projection, radial solves, inverse projection, inverse FFT).
+        """
+        st = np.zeros(5)
+        _check(lib.spp_solve_profiled(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
+                                      _vp(self.workspace.data_ptr()), _stream_ptr(stream),
+                                      st.ctypes.data_as(_dp)), "spp_solve_profiled")
+        return st
+
+    def theta_eigensystem(self, m):
+        H = np.empty((self.nth, self.nth))
+        lam = np.empty(self.nth)
+        _check(lib.spp_theta_eigensystem(self._plan, int(m), H.ctypes.data_as(_dp), lam.ctypes.data_as(_dp)),
+               "spp_theta_eigensystem")
+        return lam, H
+
+    def __del__(self):
+        p = getattr(self, "_plan", None)
+        if p is not None and p.value:
+            lib.spp_plan_destroy(p)
+            self._plan = None

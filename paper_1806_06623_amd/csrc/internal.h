@@ -1,0 +1,56 @@
+// Internal declarations shared by the host set-up code and the HIP solve path.
+#pragma once
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "sphpoisson.h"
+
+struct spp_grid_s {
+    int nr = 0, nth = 0, nphi = 0;
+    std::vector<double> r_if, th_if;
+};
+
+// Byte offsets of the device-resident plan tables (all 256-byte aligned).
+struct spp_plan_layout {
+    size_t tw = 0;      // twiddles exp(-2 pi i t / N_phi), t < N_phi: [N_phi][2]
+    size_t W = 0;       // forward projection, [M][N_theta(l)][N_theta(j)]
+    size_t H = 0;       // inverse projection, [M][N_theta(j)][N_theta(l)]
+    size_t lam = 0;     // lambda_Omega, [M][N_theta]
+    size_t beta = 0;    // outer-boundary coefficient, [M][N_theta]
+    size_t alpha = 0;   // radial face coefficients, [N_r] (last entry 0)
+    size_t V = 0;       // radial volume factors, [N_r]
+    size_t VR = 0;      // V_i R_i, [N_r]
+    size_t total = 0;
+};
+
+struct spp_plan_s {
+    int nr = 0, nth = 0, nphi = 0, nm = 0;   // nm = N_phi/2 + 1 azimuthal modes
+    std::vector<double> r_if, th_if;
+    // host tables (float64), layouts as in spp_plan_layout
+    std::vector<double> tw, W, H, lam, beta, alpha, V, VR;
+    spp_plan_layout lay;
+    size_t workspace_bytes = 0;
+    void* dev = nullptr;                       // caller-owned device copy
+};
+
+// thread-local error message helpers
+spp_status spp_fail(spp_status st, const std::string& msg);
+
+// Device entry of the FP64 solve (solve.hip).  With ev != NULL, ev[0..5]
+// are recorded on the stream before the first and after every stage.
+spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* phi, double G,
+                                void* ws, void* stream, hipEvent_t* ev = nullptr);
+
+// Number of timed stages of one solve and their names.
+constexpr int SPP_NUM_STAGES = 5;
+
+// Symmetric tridiagonal eigensolver (eigen_ql.cpp): d[n] diagonal,
+// e[n-1] off-diagonal; on return d holds the eigenvalues in ascending order
+// and Z (row-major n x n) the orthonormal eigenvectors as columns.
+bool spp_tridiag_eigen(int n, std::vector<double>& d, std::vector<double> e, std::vector<double>& Z);
+
+inline size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }

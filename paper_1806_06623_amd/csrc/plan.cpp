@@ -1,0 +1,314 @@
+// Host side of the library: grid validation, the set-up of Sec. 3.2 (geometry,
+// per-m theta eigensystems, radial and boundary tables) in float64, the device
+// layout of the plan, and the C ABI entry points other than the solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+
+#include "internal.h"
+
+static thread_local std::string g_last_error;
+
+spp_status spp_fail(spp_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+extern "C" const char* spp_last_error(void) { return g_last_error.c_str(); }
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// ---------------------------------------------------------------- grid
+extern "C" spp_status spp_grid_create(int nr, const double* r_if, int nth, const double* th_if,
+                                      int nphi, spp_grid* out)
+{
+    if (!out || !r_if || !th_if) return spp_fail(SPP_EINVAL, "spp_grid_create: NULL pointer");
+    *out = nullptr;
+    if (nr < 2 || nth < 2 || nphi < 2)
+        return spp_fail(SPP_EINVAL, "spp_grid_create: need nr >= 2, nth >= 2, nphi >= 2");
+    if (!(r_if[0] >= 0.0)) return spp_fail(SPP_EINVAL, "spp_grid_create: r_if[0] must be >= 0");
+    for (int i = 0; i < nr; ++i)
+        if (!(r_if[i + 1] > r_if[i]) || !std::isfinite(r_if[i + 1]))
+            return spp_fail(SPP_EINVAL, "spp_grid_create: r interfaces must increase strictly");
+    for (int j = 0; j < nth; ++j)
+        if (!(th_if[j + 1] > th_if[j]))
+            return spp_fail(SPP_EINVAL, "spp_grid_create: theta interfaces must increase strictly");
+    if (std::fabs(th_if[0]) > 1e-12 || std::fabs(th_if[nth] - M_PI) > 1e-12)
+        return spp_fail(SPP_EINVAL, "spp_grid_create: theta interfaces must span [0, pi]");
+    auto* g = new (std::nothrow) spp_grid_s;
+    if (!g) return spp_fail(SPP_ENOMEM, "spp_grid_create: out of host memory");
+    g->nr = nr;
+    g->nth = nth;
+    g->nphi = nphi;
+    g->r_if.assign(r_if, r_if + nr + 1);
+    g->th_if.assign(th_if, th_if + nth + 1);
+    g->th_if.front() = 0.0;
+    g->th_if.back() = M_PI;
+    *out = g;
+    return SPP_OK;
+}
+
+extern "C" void spp_grid_destroy(spp_grid g) { delete g; }
+
+// ---------------------------------------------------------------- plan
+namespace {
+
+struct Geometry {
+    std::vector<double> r, V, VR, alpha;          // radial
+    std::vector<double> th, dmu, dth, sigma;      // theta (sigma has nth+1 faces)
+};
+
+Geometry make_geometry(const spp_grid_s& g)
+{
+    Geometry G;
+    const int nr = g.nr, nth = g.nth;
+    G.r.resize(nr);
+    G.V.resize(nr);
+    G.VR.resize(nr);
+    G.alpha.assign(nr, 0.0);
+    for (int i = 0; i < nr; ++i) {
+        const double a = g.r_if[i], b = g.r_if[i + 1];
+        G.r[i] = 0.5 * (a + b);
+        // (b^3 - a^3)/3 and (b^2 - a^2)/2 in factored form (no cancellation)
+        G.V[i] = (b - a) * (b * b + a * b + a * a) / 3.0;
+        // V_i R_i = (r_{i+1/2}^2 - r_{i-1/2}^2) / (2 r_i)   (Sec. 3.1, R_i)
+        G.VR[i] = (b - a) * (b + a) / (2.0 * G.r[i]);
+    }
+    // interior radial faces: area / distance with the angular factor removed
+    for (int i = 0; i + 1 < nr; ++i) {
+        const double f = g.r_if[i + 1];
+        G.alpha[i] = f * f / (G.r[i + 1] - G.r[i]);
+    }
+    G.th.resize(nth);
+    G.dmu.resize(nth);
+    G.dth.resize(nth);
+    G.sigma.assign(nth + 1, 0.0);                 // pole faces have zero area
+    for (int j = 0; j < nth; ++j) {
+        const double a = g.th_if[j], b = g.th_if[j + 1];
+        G.th[j] = 0.5 * (a + b);
+        G.dth[j] = b - a;
+        // cos a - cos b = 2 sin((a+b)/2) sin((b-a)/2)
+        G.dmu[j] = 2.0 * std::sin(0.5 * (a + b)) * std::sin(0.5 * (b - a));
+    }
+    for (int j = 1; j < nth; ++j) G.sigma[j] = std::sin(g.th_if[j]) / (G.th[j] - G.th[j - 1]);
+    return G;
+}
+
+}  // namespace
+
+extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
+{
+    if (!g || !out) return spp_fail(SPP_EINVAL, "spp_plan_create: NULL pointer");
+    *out = nullptr;
+    if (!is_pow2(g->nphi) || g->nphi < 4 || g->nphi > 2048)
+        return spp_fail(SPP_ENOTSUP, "spp_plan_create: the GPU path needs nphi a power of two in [4, 2048]");
+    auto* p = new (std::nothrow) spp_plan_s;
+    if (!p) return spp_fail(SPP_ENOMEM, "spp_plan_create: out of host memory");
+    try {
+        const int nr = g->nr, nth = g->nth, nphi = g->nphi, nm = nphi / 2 + 1;
+        p->nr = nr;
+        p->nth = nth;
+        p->nphi = nphi;
+        p->nm = nm;
+        p->r_if = g->r_if;
+        p->th_if = g->th_if;
+        const Geometry G = make_geometry(*g);
+        p->alpha = G.alpha;
+        p->V = G.V;
+        p->VR = G.VR;
+
+        // twiddles exp(-2 pi i t / N_phi), evaluated in long double
+        p->tw.resize(2 * size_t(nphi));
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        for (int t = 0; t < nphi; ++t) {
+            const long double a = two_pi * (long double)t / (long double)nphi;
+            p->tw[2 * t] = (double)cosl(a);
+            p->tw[2 * t + 1] = (double)-sinl(a);
+        }
+
+        // per-m theta eigensystems (Sec. 3.2): K H = lambda D H with
+        // K_jj = -(sigma_{j-1/2} + sigma_{j+1/2}) + dth_j lambda_phi / sin th_j,
+        // K_{j,j+1} = sigma_{j+1/2}, D = diag(dmu), solved through the
+        // symmetric matrix D^-1/2 K D^-1/2.
+        p->W.assign(size_t(nm) * nth * nth, 0.0);
+        p->H.assign(size_t(nm) * nth * nth, 0.0);
+        p->lam.assign(size_t(nm) * nth, 0.0);
+        p->beta.assign(size_t(nm) * nth, 0.0);
+        const double dphi = 2.0 * M_PI / nphi;
+        const double ro = g->r_if[nr], rn = G.r[nr - 1];
+        const double log_ratio = std::log(ro / rn);
+        std::vector<double> isd(nth);
+        for (int j = 0; j < nth; ++j) isd[j] = 1.0 / std::sqrt(G.dmu[j]);
+
+        bool ok = true;
+        auto work = [&](int m0, int stride) {
+            std::vector<double> d(nth), e(nth > 1 ? nth - 1 : 0), Z;
+            for (int m = m0; m < nm; m += stride) {
+                const double sm = std::sin(0.5 * m * dphi) / (0.5 * dphi);
+                const double lam_phi = -sm * sm;   // eigenvalue of the phi second difference
+                for (int j = 0; j < nth; ++j)
+                    d[j] = (-(G.sigma[j] + G.sigma[j + 1]) + G.dth[j] * lam_phi / std::sin(G.th[j]))
+                           * isd[j] * isd[j];
+                for (int j = 0; j + 1 < nth; ++j) e[j] = G.sigma[j + 1] * isd[j] * isd[j + 1];
+                if (!spp_tridiag_eigen(nth, d, e, Z)) { ok = false; return; }
+                double* Hm = &p->H[size_t(m) * nth * nth];
+                double* Wm = &p->W[size_t(m) * nth * nth];
+                for (int j = 0; j < nth; ++j)
+                    for (int l = 0; l < nth; ++l) {
+                        const double h = Z[size_t(j) * nth + l] * isd[j];   // H = D^-1/2 V
+                        Hm[size_t(j) * nth + l] = h;
+                        Wm[size_t(l) * nth + j] = h * G.dmu[j];            // H^-1 = H^T D
+                    }
+                for (int l = 0; l < nth; ++l) {
+                    const double lam = d[l];
+                    p->lam[size_t(m) * nth + l] = lam;
+                    // outer face: flux / (dmu dphi) = -beta f_N with
+                    // beta = p r_o (r_o / r_N)^-p, p = (1 + sqrt(1 - 4 lambda))/2
+                    const double pp = 0.5 * (1.0 + std::sqrt(std::max(0.0, 1.0 - 4.0 * lam)));
+                    p->beta[size_t(m) * nth + l] = pp * ro * std::exp(-pp * log_ratio);
+                }
+            }
+        };
+        const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t, nthreads);
+        work(0, nthreads);
+        for (auto& th : pool) th.join();
+        if (!ok) {
+            delete p;
+            return spp_fail(SPP_EDEVICE, "spp_plan_create: theta eigen iteration did not converge");
+        }
+
+        // device layout
+        spp_plan_layout& L = p->lay;
+        size_t off = 0;
+        auto take = [&](size_t n_doubles) {
+            const size_t o = off;
+            off = spp_align256(off + n_doubles * sizeof(double));
+            return o;
+        };
+        L.tw = take(p->tw.size());
+        L.W = take(p->W.size());
+        L.H = take(p->H.size());
+        L.lam = take(p->lam.size());
+        L.beta = take(p->beta.size());
+        L.alpha = take(p->alpha.size());
+        L.V = take(p->V.size());
+        L.VR = take(p->VR.size());
+        L.total = off;
+        const size_t field = spp_align256(size_t(nr) * nth * nphi * sizeof(double));
+        p->workspace_bytes = 2 * field;
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return spp_fail(SPP_ENOMEM, "spp_plan_create: out of host memory");
+    }
+    *out = p;
+    return SPP_OK;
+}
+
+extern "C" void spp_plan_destroy(spp_plan p) { delete p; }
+
+extern "C" spp_status spp_plan_device_bytes(spp_plan p, size_t* plan_bytes, size_t* workspace_bytes)
+{
+    if (!p) return spp_fail(SPP_EINVAL, "spp_plan_device_bytes: NULL plan");
+    if (plan_bytes) *plan_bytes = p->lay.total;
+    if (workspace_bytes) *workspace_bytes = p->workspace_bytes;
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi)
+{
+    if (!p) return spp_fail(SPP_EINVAL, "spp_plan_shape: NULL plan");
+    if (nr) *nr = p->nr;
+    if (nth) *nth = p->nth;
+    if (nphi) *nphi = p->nphi;
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
+{
+    if (!p || !plan_dev) return spp_fail(SPP_EINVAL, "spp_plan_upload: NULL pointer");
+    if (reinterpret_cast<uintptr_t>(plan_dev) & 255)
+        return spp_fail(SPP_EINVAL, "spp_plan_upload: plan buffer must be 256-byte aligned");
+    std::vector<unsigned char> img(p->lay.total, 0);
+    auto put = [&](size_t off, const std::vector<double>& v) {
+        std::memcpy(img.data() + off, v.data(), v.size() * sizeof(double));
+    };
+    put(p->lay.tw, p->tw);
+    put(p->lay.W, p->W);
+    put(p->lay.H, p->H);
+    put(p->lay.lam, p->lam);
+    put(p->lay.beta, p->beta);
+    put(p->lay.alpha, p->alpha);
+    put(p->lay.V, p->V);
+    put(p->lay.VR, p->VR);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(plan_dev, img.data(), img.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return spp_fail(SPP_EDEVICE, std::string("spp_plan_upload: ") + hipGetErrorString(e));
+    p->dev = plan_dev;
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_theta_eigensystem(spp_plan p, int m, double* H, double* lam)
+{
+    if (!p || !H || !lam) return spp_fail(SPP_EINVAL, "spp_theta_eigensystem: NULL pointer");
+    if (m < 0 || m >= p->nm) return spp_fail(SPP_EINVAL, "spp_theta_eigensystem: m out of range");
+    const size_t n = p->nth;
+    std::memcpy(H, &p->H[m * n * n], n * n * sizeof(double));
+    std::memcpy(lam, &p->lam[m * n], n * sizeof(double));
+    return SPP_OK;
+}
+
+static spp_status validate_solve(const char* who, spp_plan p, const double* rho_dev, const double* phi_dev,
+                                 double G, const void* workspace_dev)
+{
+    const std::string w(who);
+    if (!p || !rho_dev || !phi_dev || !workspace_dev) return spp_fail(SPP_EINVAL, w + ": NULL pointer");
+    if (!p->dev) return spp_fail(SPP_ESTATE, w + ": plan not uploaded");
+    if (reinterpret_cast<uintptr_t>(workspace_dev) & 255)
+        return spp_fail(SPP_EINVAL, w + ": workspace must be 256-byte aligned");
+    if (!std::isfinite(G)) return spp_fail(SPP_EINVAL, w + ": G must be finite");
+    const size_t n = size_t(p->nr) * p->nth * p->nphi * sizeof(double);
+    const char *a = reinterpret_cast<const char*>(rho_dev), *b = reinterpret_cast<const char*>(phi_dev);
+    if (a < b + n && b < a + n) return spp_fail(SPP_EINVAL, w + ": rho and phi must not overlap");
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double G,
+                                void* workspace_dev, void* stream)
+{
+    const spp_status st = validate_solve("spp_solve", p, rho_dev, phi_dev, G, workspace_dev);
+    if (st != SPP_OK) return st;
+    return spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream);
+}
+
+extern "C" spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev, double G,
+                                         void* workspace_dev, void* stream, double* stage_ms)
+{
+    if (!stage_ms) return spp_fail(SPP_EINVAL, "spp_solve_profiled: NULL stage_ms");
+    spp_status st = validate_solve("spp_solve_profiled", p, rho_dev, phi_dev, G, workspace_dev);
+    if (st != SPP_OK) return st;
+    hipEvent_t ev[SPP_NUM_STAGES + 1] = {};
+    int made = 0;
+    for (; made <= SPP_NUM_STAGES; ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) break;
+    if (made <= SPP_NUM_STAGES) st = spp_fail(SPP_EDEVICE, "spp_solve_profiled: hipEventCreate failed");
+    if (st == SPP_OK) st = spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream, ev);
+    if (st == SPP_OK && hipEventSynchronize(ev[SPP_NUM_STAGES]) != hipSuccess)
+        st = spp_fail(SPP_EDEVICE, "spp_solve_profiled: hipEventSynchronize failed");
+    for (int k = 0; st == SPP_OK && k < SPP_NUM_STAGES; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess)
+            st = spp_fail(SPP_EDEVICE, "spp_solve_profiled: hipEventElapsedTime failed");
+        stage_ms[k] = ms;
+    }
+    for (int k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
+    return st;
+}

@@ -1,0 +1,332 @@
+// FP64 solve path for gfx950: the five stages of Sec. 3.2 as HIP kernels.
+//
+//   k_rfft_fwd   s = 4 pi G rho, real FFT along phi       rho[i][j][k] -> X[q][i][j]
+//   k_proj_f64   s^_q = W_m s~_q  (MFMA, batched over q)  X[q][i][j]   -> Y[q][i][l]
+//   k_radial     Delta_r f + R_i lambda f = s^ per (q,l)   Y[q][i][l]   -> Y (in place)
+//   k_proj_f64   g_q = H_m f_q                             Y[q][i][l]   -> X[q][i][j]
+//   k_rfft_inv   inverse real FFT along phi                X[q][i][j]   -> phi[i][j][k]
+//
+// q runs over the N_phi real Fourier components (cos and sin parts of every
+// mode m, see fft.hip.h); both parts of a mode share the eigensystem of m.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "fft.hip.h"
+#include "internal.h"
+
+namespace {
+
+// ------------------------------------------------------------------ FFT
+template <int N>
+__global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
+                                                  const c64* __restrict__ tw, double scale, int nlines)
+{
+    using S = FftShape<N>;
+    constexpr int N2 = S::N2, T = S::T, JB = S::JB;
+    __shared__ c64 lds[JB * N2];
+    const int L0 = blockIdx.x * JB;
+    const int nl = min(JB, nlines - L0);
+
+    // contiguous lines -> LDS (a real line of N doubles is N2 complex values)
+    const double2* src = reinterpret_cast<const double2*>(rho + size_t(L0) * N);
+    for (int e = threadIdx.x; e < JB * N2; e += 256) {
+        double2 v = {0.0, 0.0};
+        if (e < nl * N2) v = src[e];
+        lds[e] = {v.x * scale, v.y * scale};
+    }
+    __syncthreads();
+
+    const int line = threadIdx.x / T, tid = threadIdx.x % T;
+    fft_passes<N2, 1, T, S::E>(lds + line * N2, tid, tw);
+
+    // split Z into the half spectrum X_m and store halfcomplex planes
+    const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
+    if (l < nl) {
+        const c64* Z = lds + l * N2;
+        const size_t plane = size_t(nlines);
+        double* out = X + L0 + l;
+        for (int p = grp; p <= N2 / 2; p += T) {
+            const c64 a = Z[p];
+            const c64 b = Z[(N2 - p) & (N2 - 1)];
+            // X_p = (a + conj b)/2 + w^p (a - conj b)/(2i)
+            const c64 A = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+            const c64 B = {0.5 * (a.y + b.y), -0.5 * (a.x - b.x)};
+            const c64 w = tw[p];
+            const c64 Xp = cadd(A, cmul(w, B));
+            // partner X_{N2-p} = conj(A) - conj(w) * conj-swapped B
+            const c64 A2 = cconj(A);
+            const c64 B2 = {B.x, -B.y};
+            const c64 Xq = csub(A2, cmul(cconj(w), B2));
+            if (p == 0) {
+                out[0] = Xp.x;                         // Re X_0
+                out[size_t(N2) * plane] = Xq.x;        // Re X_{N/2}
+            } else if (2 * p == N2) {
+                out[size_t(p) * plane] = Xp.x;
+                out[size_t(N - p) * plane] = Xp.y;
+            } else {
+                out[size_t(p) * plane] = Xp.x;
+                out[size_t(N - p) * plane] = Xp.y;
+                out[size_t(N2 - p) * plane] = Xq.x;
+                out[size_t(N2 + p) * plane] = Xq.y;
+            }
+        }
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
+                                                  const c64* __restrict__ tw, int nlines)
+{
+    using S = FftShape<N>;
+    constexpr int N2 = S::N2, T = S::T, JB = S::JB;
+    __shared__ c64 lds[JB * N2];
+    const int L0 = blockIdx.x * JB;
+    const int nl = min(JB, nlines - L0);
+
+    // rebuild Z_m = [X_m + conj X_{N2-m}] + i w^-m [X_m - conj X_{N2-m}] and
+    // store conj(Z): the inverse transform is conj(FFT(conj Z)).
+    const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
+    {
+        c64* Z = lds + l * N2;
+        const size_t plane = size_t(nlines);
+        const double* in = X + L0 + l;
+        const bool live = l < nl;
+        for (int p = grp; p <= N2 / 2; p += T) {
+            c64 xp, xq;   // X_p and X_{N2-p}
+            if (p == 0) {
+                xp = {live ? in[0] : 0.0, 0.0};
+                xq = {live ? in[size_t(N2) * plane] : 0.0, 0.0};
+            } else {
+                xp = {live ? in[size_t(p) * plane] : 0.0, live ? in[size_t(N - p) * plane] : 0.0};
+                xq = {live ? in[size_t(N2 - p) * plane] : 0.0, live ? in[size_t(N2 + p) * plane] : 0.0};
+            }
+            const c64 wc = cconj(tw[p]);               // w^-p
+            const c64 Ep = cadd(xp, cconj(xq)), Dp = csub(xp, cconj(xq));
+            const c64 iwD = cmul({-wc.y, wc.x}, Dp);   // i w^-p D
+            Z[p] = cconj(cadd(Ep, iwD));
+            if (p != 0 && 2 * p != N2) {
+                // Z_{N2-p} with w^-(N2-p) = -w^p
+                const c64 Eq = cadd(xq, cconj(xp)), Dq = csub(xq, cconj(xp));
+                const c64 w = tw[p];
+                const c64 iwDq = cmul({w.y, -w.x}, Dq);  // i * (-w^p) * Dq
+                Z[N2 - p] = cconj(cadd(Eq, iwDq));
+            }
+        }
+    }
+    __syncthreads();
+
+    const int line = threadIdx.x / T, tid = threadIdx.x % T;
+    fft_passes<N2, 1, T, S::E>(lds + line * N2, tid, tw);
+
+    // x_{2n} = Re z_n, x_{2n+1} = Im z_n with z = conj(FFT(conj Z))
+    double2* dst = reinterpret_cast<double2*>(phi + size_t(L0) * N);
+    for (int e = threadIdx.x; e < nl * N2; e += 256) {
+        const c64 v = lds[e];
+        dst[e] = double2{v.x, -v.y};
+    }
+}
+
+// ------------------------------------------------------------------ projection GEMM (MFMA f64)
+// C[q][i][n] = sum_k A[q][i][k] * B[m(q)][n][k], i < M, n, k < K (= N_theta).
+// Workgroup tile 64 x 64, four waves of 32 x 32, v_mfma_f64_16x16x4 with
+// K staged through LDS in chunks of 16 (k-major, padded against bank
+// conflicts).  Operand layouts of the 16x16x4 f64 MFMA: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the 16x16 result lives in 4
+// registers per lane, register v holding row (l / 16) + 4 v, column l % 16.
+constexpr int PBM = 64, PBN = 64, PBK = 16, PPAD = 16;
+
+__global__ __launch_bounds__(256) void k_proj_f64(const double* __restrict__ A, const double* __restrict__ B,
+                                                  double* __restrict__ C, int M, int K, int nphi)
+{
+    const int q = blockIdx.z;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const double* Aq = A + size_t(q) * M * K;
+    const double* Bm = B + size_t(m) * K * K;
+    double* Cq = C + size_t(q) * M * K;
+    const int i0 = blockIdx.y * PBM, n0 = blockIdx.x * PBN;
+
+    __shared__ double As[PBK][PBM + PPAD];
+    __shared__ double Bs[PBK][PBN + PPAD];
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lrow = t >> 2, lk = (t & 3) * 4;   // loader: one row, four k
+
+    using d4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = 0; k0 < K; k0 += PBK) {
+        {
+            const int gi = i0 + lrow, gn = n0 + lrow;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int gk = k0 + lk + c;
+                As[lk + c][lrow] = (gi < M && gk < K) ? Aq[size_t(gi) * K + gk] : 0.0;
+                Bs[lk + c][lrow] = (gn < K && gk < K) ? Bm[size_t(gn) * K + gk] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < PBK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[2], b[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) a[r] = As[kr][wm * 32 + r * 16 + (lane & 15)];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) b[c] = Bs[kr][wn * 32 + c * 16 + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int col = n0 + wn * 32 + c * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = i0 + wm * 32 + r * 16 + (lane >> 4) + 4 * v;
+                if (row < M && col < K) Cq[size_t(row) * K + col] = acc[r][c][v];
+            }
+        }
+}
+
+// ------------------------------------------------------------------ radial tridiagonal
+// One lane per (q, l) system; rows scaled by V_i so the matrix is symmetric:
+//   alpha_{i-1} f_{i-1} + (-(alpha_{i-1} + alpha_i) + V_i R_i lambda) f_i
+//     + alpha_i f_{i+1} = V_i s^_i,
+// with alpha_{-1} = 0 and the outermost alpha replaced by beta(lambda).
+// Forward elimination stores y_i in place and 1/w_i in `piv`; the back
+// substitution then runs from the outer shell inwards.
+__global__ __launch_bounds__(256) void k_radial(double* __restrict__ Y, double* __restrict__ piv,
+                                                const double* __restrict__ lam, const double* __restrict__ beta,
+                                                const double* __restrict__ alpha, const double* __restrict__ V,
+                                                const double* __restrict__ VR, int nr, int nth, int nphi)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nphi * nth) return;
+    const int q = gid / nth, l = gid - q * nth;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const double lm = lam[m * nth + l];
+    const double bo = beta[m * nth + l];
+    const size_t stride = size_t(nth);
+    double* y = Y + size_t(q) * nr * nth + l;
+    double* pv = piv + size_t(q) * nr * nth + l;
+
+    double a_prev = 0.0, w_prev = 1.0, y_prev = 0.0, inv_prev = 0.0;
+    for (int i = 0; i < nr; ++i) {
+        const double ai = (i + 1 < nr) ? alpha[i] : bo;
+        const double diag = -(a_prev + ai) + VR[i] * lm;
+        const double rhs = V[i] * y[i * stride];
+        const double lf = a_prev * inv_prev;          // a_prev / w_prev
+        const double w = diag - lf * a_prev;
+        const double yi = rhs - lf * y_prev;
+        const double inv = 1.0 / w;
+        y[i * stride] = yi;
+        pv[i * stride] = inv;
+        a_prev = ai;
+        w_prev = w;
+        y_prev = yi;
+        inv_prev = inv;
+    }
+    (void)w_prev;
+    double f_next = 0.0;
+    for (int i = nr - 1; i >= 0; --i) {
+        const double ai = (i + 1 < nr) ? alpha[i] : 0.0;
+        const double f = (y[i * stride] - ai * f_next) * pv[i * stride];
+        y[i * stride] = f;
+        f_next = f;
+    }
+}
+
+template <int N>
+void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
+                     hipStream_t s)
+{
+    using S = FftShape<N>;
+    const int blocks = (nlines + S::JB - 1) / S::JB;
+    if (forward)
+        hipLaunchKernelGGL(k_rfft_fwd<N>, dim3(blocks), dim3(256), 0, s, in, out, tw, scale, nlines);
+    else
+        hipLaunchKernelGGL(k_rfft_inv<N>, dim3(blocks), dim3(256), 0, s, in, out, tw, nlines);
+}
+
+bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
+                hipStream_t s)
+{
+    switch (nphi) {
+#define SPP_FFT_CASE(n) \
+    case n: launch_fft_pair<n>(forward, in, out, tw, scale, nlines, s); return true;
+        SPP_FFT_CASE(4)
+        SPP_FFT_CASE(8)
+        SPP_FFT_CASE(16)
+        SPP_FFT_CASE(32)
+        SPP_FFT_CASE(64)
+        SPP_FFT_CASE(128)
+        SPP_FFT_CASE(256)
+        SPP_FFT_CASE(512)
+        SPP_FFT_CASE(1024)
+        SPP_FFT_CASE(2048)
+#undef SPP_FFT_CASE
+    default: return false;
+    }
+}
+
+}  // namespace
+
+spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* phi, double G, void* ws,
+                                void* stream, hipEvent_t* ev)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char* base = static_cast<const char*>(p->dev);
+    const c64* tw = reinterpret_cast<const c64*>(base + p->lay.tw);
+    const double* W = reinterpret_cast<const double*>(base + p->lay.W);
+    const double* H = reinterpret_cast<const double*>(base + p->lay.H);
+    const double* lam = reinterpret_cast<const double*>(base + p->lay.lam);
+    const double* beta = reinterpret_cast<const double*>(base + p->lay.beta);
+    const double* alpha = reinterpret_cast<const double*>(base + p->lay.alpha);
+    const double* V = reinterpret_cast<const double*>(base + p->lay.V);
+    const double* VR = reinterpret_cast<const double*>(base + p->lay.VR);
+
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    const int nlines = nr * nth;
+    const size_t field = spp_align256(size_t(nlines) * nphi * sizeof(double));
+    double* X = static_cast<double*>(ws);
+    double* Y = reinterpret_cast<double*>(static_cast<char*>(ws) + field);
+
+    // s~ scaled so that the inverse transform needs no 1/N: 4 pi G / N_phi
+    const double scale = 4.0 * M_PI * G / nphi;
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], s);
+    };
+    mark(0);
+    if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s))
+        return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
+    mark(1);
+    const dim3 pgrid((nth + PBN - 1) / PBN, (nr + PBM - 1) / PBM, nphi);
+    hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
+    mark(2);
+    const int nsys = nphi * nth;
+    hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR, nr,
+                       nth, nphi);
+    mark(3);
+    hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
+    mark(4);
+    launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s);
+    mark(5);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve: ") + hipGetErrorString(e));
+    return SPP_OK;
+}
