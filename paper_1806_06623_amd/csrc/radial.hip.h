@@ -1,0 +1,196 @@
+// Radial tridiagonal solves (Sec. 3.2: Delta_r f + R_i lambda_Omega f = s^ for
+// every (m, l), with the asymptotic outer boundary condition), float64.
+//
+// Every row is scaled by V_i, which makes each system symmetric:
+//   alpha_{i-1} f_{i-1} + b_i f_i + alpha_i f_{i+1} = V_i s^_i,
+//   b_i = -(alpha_{i-1} + alpha_i) + V_i R_i lambda   (alpha_{-1} = 0),
+// and on the outermost row the missing face coefficient is beta(lambda).
+//
+// Partition method, one workgroup per 32 systems and P <= 32 chunks of rows:
+// lane (s, p) holds rows [s_p, s_{p+1}) of system s in registers.  Row s_p is
+// a separator; the interior rows of a chunk are eliminated locally, which
+// expresses its first and last interior unknowns in terms of the two
+// separators around it.  Substituting those into the separator rows gives a
+// P x P tridiagonal system per system (the Schur complement), solved by one
+// lane through LDS; each lane then back-substitutes its interior with the
+// separators known.  Every value is read from and written to HBM once.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace radial {
+
+constexpr int SYS = 32;     // systems per workgroup (consecutive (q, l) pairs)
+constexpr int PMAX = 32;    // chunks per system
+
+struct Coef {
+    const double* alpha;    // alpha_i, coupling rows i and i+1; alpha[nr-1] = 0
+    const double* V;
+    const double* VR;
+    int nr;
+    __device__ __forceinline__ double off(int i) const { return alpha[i]; }
+    // diagonal of row i for eigenvalue lm and outer coefficient bo
+    __device__ __forceinline__ double diag(int i, double lm, double bo) const
+    {
+        const double am = i > 0 ? alpha[i - 1] : 0.0;
+        double b = -(am + alpha[i]) + VR[i] * lm;
+        if (i == nr - 1) b -= bo;
+        return b;
+    }
+};
+
+template <int CH>
+__global__ __launch_bounds__(1024) void k_radial_part(double* __restrict__ Y, const double* __restrict__ lam,
+                                                      const double* __restrict__ beta, Coef cf, int nth,
+                                                      int nphi, int P)
+{
+    __shared__ double own[3][PMAX][SYS];   // separator row p: B (diag part), C, D
+    __shared__ double nxt[3][PMAX][SYS];   // contribution of chunk p to row p+1: A, B add, D sub
+    __shared__ double xs[PMAX + 1][SYS];
+
+    const int nr = cf.nr;
+    const int t = threadIdx.x;
+    const int sl = t % SYS, p = t / SYS;
+    const int nsys = nphi * nth;
+    const int sys_raw = blockIdx.x * SYS + sl;
+    const bool live = sys_raw < nsys;
+    const int sys = live ? sys_raw : nsys - 1;
+    const int q = sys / nth, l = sys - q * nth;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const double lm = lam[m * nth + l];
+    const double bo = beta[m * nth + l];
+    const bool active = p < P;
+
+    const int s0 = active ? (p * nr) / P : 0;
+    const int s1 = active ? ((p + 1) * nr) / P : 0;
+    const int n = s1 - s0 - 1;                  // interior rows s0+1 .. s1-1
+    const bool last = p == P - 1;
+    double* col = Y + size_t(q) * nr * nth + l;
+
+    double d[CH];
+    double invw[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        d[k] = 0.0;
+        invw[k] = 0.0;
+        if (active && k <= n) d[k] = cf.V[s0 + k] * col[size_t(s0 + k) * nth];
+    }
+
+    // ---- pass 1: eliminate the interior in both directions
+    double Yf = 0.0, Uf = 0.0, Vf = 1.0, Yl = 0.0, Ul = 1.0, Vl = 0.0;
+    const double oL = (active && s0 + 1 < nr) ? cf.off(s0) : 0.0;                 // s0 <-> s0+1
+    const double oR = (active && !last) ? cf.off(s1 - 1) : 0.0;                  // s1-1 <-> s1
+    if (active && n >= 1) {
+        // forward (LU): pivots w_k, running L^-1 d and L^-1 (-oL e_1)
+        double w = 1.0, zf = 0.0, uf = 0.0, iwn = 0.0;
+#pragma unroll
+        for (int k = 1; k < CH; ++k) {
+            if (k <= n) {
+                const int i = s0 + k;
+                if (k == 1) {
+                    w = cf.diag(i, lm, bo);
+                    zf = d[1];
+                    uf = -oL;
+                } else {
+                    const double o = cf.off(i - 1);
+                    const double mult = o * invw[k - 1];
+                    w = cf.diag(i, lm, bo) - mult * o;
+                    zf = d[k] - mult * zf;
+                    uf = -mult * uf;
+                }
+                invw[k] = 1.0 / w;
+                iwn = invw[k];
+            }
+        }
+        Yl = zf * iwn;
+        Ul = uf * iwn;
+        Vl = -oR * iwn;
+        // backward (UL): pivots from the last interior row upwards
+        double wh = 1.0, zh = 0.0, vh = 0.0, iwh = 0.0;
+#pragma unroll
+        for (int k = CH - 1; k >= 1; --k) {
+            if (k <= n) {
+                const int i = s0 + k;
+                if (k == n) {
+                    wh = cf.diag(i, lm, bo);
+                    zh = d[k];
+                    vh = -oR;
+                } else {
+                    const double o = cf.off(i);
+                    const double mult = o * iwh;
+                    wh = cf.diag(i, lm, bo) - mult * o;
+                    zh = d[k] - mult * zh;
+                    vh = -mult * vh;
+                }
+                iwh = 1.0 / wh;
+            }
+        }
+        Yf = zh * iwh;
+        Vf = vh * iwh;
+        Uf = -oL * iwh;
+    }
+
+    // ---- reduced system over the separators s_0..s_{P-1}
+    if (active) {
+        const double bs = cf.diag(s0, lm, bo);
+        own[0][p][sl] = bs + oL * Uf;
+        own[1][p][sl] = oL * Vf;
+        own[2][p][sl] = d[0] - oL * Yf;
+        nxt[0][p][sl] = oR * Ul;
+        nxt[1][p][sl] = oR * Vl;
+        nxt[2][p][sl] = oR * Yl;
+    }
+    __syncthreads();
+    if (t < SYS) {
+        // Thomas over the P separator rows of system sl,
+        //   A_r x_{r-1} + B_r x_r + C_r x_{r+1} = D_r;
+        // the eliminated C'_r, D'_r overwrite own[1][r], own[2][r].
+        double cp = 0.0, dp = 0.0;
+        for (int r = 0; r < P; ++r) {
+            double B = own[0][r][sl], D = own[2][r][sl];
+            const double C = own[1][r][sl];
+            if (r > 0) {
+                const double A = nxt[0][r - 1][sl];
+                B += nxt[1][r - 1][sl] - A * cp;
+                D -= nxt[2][r - 1][sl] + A * dp;
+            }
+            const double ib = 1.0 / B;
+            cp = C * ib;
+            dp = D * ib;
+            own[1][r][sl] = cp;
+            own[2][r][sl] = dp;
+        }
+        double x = 0.0;
+        for (int r = P - 1; r >= 0; --r) {
+            x = own[2][r][sl] - own[1][r][sl] * x;
+            xs[r][sl] = x;
+        }
+    }
+    __syncthreads();
+
+    // ---- pass 2: interior with both separators known
+    if (active) {
+        const double xL = xs[p][sl];
+        const double xR = last ? 0.0 : xs[p + 1][sl];
+        if (live) col[size_t(s0) * nth] = xL;
+        if (n >= 1) {
+            d[1] -= oL * xL;
+#pragma unroll
+            for (int k = 1; k < CH; ++k)
+                if (k == n) d[k] -= oR * xR;
+#pragma unroll
+            for (int k = 2; k < CH; ++k)
+                if (k <= n) d[k] -= cf.off(s0 + k - 1) * invw[k - 1] * d[k - 1];
+            double xn = 0.0;
+#pragma unroll
+            for (int k = CH - 1; k >= 1; --k) {
+                if (k <= n) {
+                    const double up = k < n ? cf.off(s0 + k) * xn : 0.0;
+                    xn = (d[k] - up) * invw[k];
+                    if (live) col[size_t(s0 + k) * nth] = xn;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace radial

@@ -15,6 +15,7 @@
 
 #include "fft.hip.h"
 #include "internal.h"
+#include "radial.hip.h"
 
 namespace {
 
@@ -251,6 +252,29 @@ __global__ __launch_bounds__(256) void k_radial(double* __restrict__ Y, double* 
     }
 }
 
+// Partitioned radial solve for N_r <= 32 * 20; returns false above that.
+bool launch_radial_part(double* Y, const double* lam, const double* beta, const double* alpha, const double* V,
+                        const double* VR, int nr, int nth, int nphi, hipStream_t s)
+{
+    const int P = nr < radial::PMAX ? nr : radial::PMAX;
+    const int ch = (nr + P - 1) / P;
+    const radial::Coef cf{alpha, V, VR, nr};
+    const int nsys = nphi * nth;
+    const dim3 grid((nsys + radial::SYS - 1) / radial::SYS), block(radial::SYS * radial::PMAX);
+#define SPP_RADIAL_CASE(C)                                                                             \
+    if (ch <= C) {                                                                                     \
+        hipLaunchKernelGGL(radial::k_radial_part<C>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); \
+        return true;                                                                                   \
+    }
+    // capacities whose register arrays stay in VGPRs (no scratch) at 1024 threads
+    SPP_RADIAL_CASE(4)
+    SPP_RADIAL_CASE(8)
+    SPP_RADIAL_CASE(18)
+    SPP_RADIAL_CASE(20)
+#undef SPP_RADIAL_CASE
+    return false;
+}
+
 template <int N>
 void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
                      hipStream_t s)
@@ -319,8 +343,9 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
     hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
     mark(2);
     const int nsys = nphi * nth;
-    hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR, nr,
-                       nth, nphi);
+    if (!launch_radial_part(Y, lam, beta, alpha, V, VR, nr, nth, nphi, s))
+        hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR,
+                           nr, nth, nphi);
     mark(3);
     hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
     mark(4);
