@@ -15,6 +15,7 @@
 
 #include "fft.hip.h"
 #include "internal.h"
+#include "proj.hip.h"
 #include "radial.hip.h"
 
 namespace {
@@ -252,6 +253,40 @@ __global__ __launch_bounds__(256) void k_radial(double* __restrict__ Y, double* 
     }
 }
 
+// Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
+bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s)
+{
+    int rn = (K + 15) / 16;
+    if (rn > 8) return false;
+    rn = rn <= 1 ? 1 : rn <= 2 ? 2 : rn <= 4 ? 4 : 8;
+    const int rm = rn == 8 ? 1 : rn == 4 ? 2 : 4;
+    const int groups = (M + 16 * rm - 1) / (16 * rm);
+    // one workgroup per CU at a time for the largest tile (B_m fills most of
+    // the LDS): split the rows of a component only when there are fewer
+    // components than CUs
+    int splits = (256 + nphi - 1) / nphi;
+    const int maxsplits = (groups + proj::NWAVES - 1) / proj::NWAVES;
+    if (splits > maxsplits) splits = maxsplits;
+    if (splits < 1) splits = 1;
+    const dim3 grid(splits, nphi), block(proj::NTHREADS);
+    const bool kvec = (K % 32) == 0;
+#define SPP_PROJ_CASE(RN, RM)                                                                              \
+    case RN:                                                                                               \
+        if (kvec)                                                                                          \
+            hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, true>), grid, block, 0, s, A, B, C, M, K, nphi, splits);  \
+        else                                                                                               \
+            hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, false>), grid, block, 0, s, A, B, C, M, K, nphi, splits); \
+        break;
+    switch (rn) {
+        SPP_PROJ_CASE(1, 4)
+        SPP_PROJ_CASE(2, 4)
+        SPP_PROJ_CASE(4, 2)
+        SPP_PROJ_CASE(8, 1)
+    }
+#undef SPP_PROJ_CASE
+    return true;
+}
+
 // Partitioned radial solve for N_r <= 32 * 20; returns false above that.
 bool launch_radial_part(double* Y, const double* lam, const double* beta, const double* alpha, const double* V,
                         const double* VR, int nr, int nth, int nphi, hipStream_t s)
@@ -340,14 +375,16 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
     mark(1);
     const dim3 pgrid((nth + PBN - 1) / PBN, (nr + PBM - 1) / PBM, nphi);
-    hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
+    if (!launch_proj(X, W, Y, nr, nth, nphi, s))
+        hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
     mark(2);
     const int nsys = nphi * nth;
     if (!launch_radial_part(Y, lam, beta, alpha, V, VR, nr, nth, nphi, s))
         hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR,
                            nr, nth, nphi);
     mark(3);
-    hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
+    if (!launch_proj(Y, H, X, nr, nth, nphi, s))
+        hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
     mark(4);
     launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s);
     mark(5);
