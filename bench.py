@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--nr", type=int, default=550)
     ap.add_argument("--nth", type=int, default=128)
     ap.add_argument("--nphi", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run torch's device copy of one field (5 times), to calibrate the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver is built and timed on a single MI355X "
@@ -92,6 +95,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = args.nr * args.nth * args.nphi
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
+                                               "copies": 5}}), flush=True)
+        return
     import paper_1806_06623_amd as spp
     import synthetic
 

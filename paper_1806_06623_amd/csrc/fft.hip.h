@@ -62,6 +62,15 @@ template <> __device__ __forceinline__ void dft<8>(c64* v)
     v[7] = csub(e[3], o3);
 }
 
+// LDS index of complex element i of a line: one pad slot after every 8
+// elements, so that the radix-8 pass (which writes 8 consecutive elements per
+// thread) and the transposed accesses of the split step fall on distinct
+// banks.  Lines are LS complex values apart, LS = padded length + 1.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+template <int N2> struct LineStride {
+    static constexpr int LS = N2 + N2 / 8 + 1;
+};
+
 // One Stockham autosort pass of radix R over a line of N2 complex values in
 // LDS, processed by T threads (tid = 0..T-1).  Ns is the length of the
 // sub-transforms already done.  tw[t] = exp(-2 pi i t / (2 N2)).
@@ -78,7 +87,7 @@ __device__ __forceinline__ void stockham_pass(c64* line, int tid, const c64* __r
         const int b = tid + u * T;
         const int k = b % Ns;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[u][r] = line[b + r * NB];
+        for (int r = 0; r < R; ++r) v[u][r] = line[pidx(b + r * NB)];
         if (Ns > 1) {
 #pragma unroll
             for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], tw[r * k * TWS]);
@@ -92,7 +101,7 @@ __device__ __forceinline__ void stockham_pass(c64* line, int tid, const c64* __r
         const int k = b % Ns;
         const int base = (b / Ns) * Ns * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) line[base + r * Ns] = v[u][r];
+        for (int r = 0; r < R; ++r) line[pidx(base + r * Ns)] = v[u][r];
     }
     __syncthreads();
 }

@@ -6,26 +6,37 @@
 //   b_i = -(alpha_{i-1} + alpha_i) + V_i R_i lambda   (alpha_{-1} = 0),
 // and on the outermost row the missing face coefficient is beta(lambda).
 //
-// Partition method, one workgroup per 32 systems and P <= 32 chunks of rows:
+// Partition method, one workgroup per 16 systems and P <= 32 chunks of rows:
 // lane (s, p) holds rows [s_p, s_{p+1}) of system s in registers.  Row s_p is
 // a separator; the interior rows of a chunk are eliminated locally, which
 // expresses its first and last interior unknowns in terms of the two
 // separators around it.  Substituting those into the separator rows gives a
-// P x P tridiagonal system per system (the Schur complement), solved by one
-// lane through LDS; each lane then back-substitutes its interior with the
-// separators known.  Every value is read from and written to HBM once.
+// P x P tridiagonal system per system (the Schur complement), solved by
+// parallel cyclic reduction over the P lanes of the system through LDS; each
+// lane then back-substitutes its interior with the separators known.  Every
+// value is read from and written to HBM once.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace radial {
 
-constexpr int SYS = 32;     // systems per workgroup (consecutive (q, l) pairs)
+constexpr int SYS = 16;     // systems per workgroup (consecutive (q, l) pairs)
 constexpr int PMAX = 32;    // chunks per system
+constexpr int THREADS = SYS * PMAX;
+
+constexpr int NRMAX = 640;  // largest N_r of the partitioned kernel (PMAX * 20)
 
 struct Coef {
     const double* alpha;    // alpha_i, coupling rows i and i+1; alpha[nr-1] = 0
     const double* V;
     const double* VR;
+    int nr;
+};
+
+// Per-row coefficients staged in LDS once per workgroup.
+struct RowCoef {
+    const double* alpha;    // LDS
+    const double* VR;       // LDS
     int nr;
     __device__ __forceinline__ double off(int i) const { return alpha[i]; }
     // diagonal of row i for eigenvalue lm and outer coefficient bo
@@ -38,16 +49,35 @@ struct Coef {
     }
 };
 
+// 1/w from the hardware reciprocal estimate refined by two Newton steps
+// (the error roughly squares each step, ending at the last bit of float64).
+__device__ __forceinline__ double recip(double w)
+{
+    double y = __builtin_amdgcn_rcp(w);
+    double e = __builtin_fma(-w, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-w, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// 512 threads and at most 128 VGPRs per lane: two workgroups per CU.
 template <int CH>
-__global__ __launch_bounds__(1024) void k_radial_part(double* __restrict__ Y, const double* __restrict__ lam,
-                                                      const double* __restrict__ beta, Coef cf, int nth,
+__global__ __launch_bounds__(THREADS, 4) void k_radial_part(double* __restrict__ Y, const double* __restrict__ lam,
+                                                      const double* __restrict__ beta, Coef tab, int nth,
                                                       int nphi, int P)
 {
     __shared__ double own[3][PMAX][SYS];   // separator row p: B (diag part), C, D
     __shared__ double nxt[3][PMAX][SYS];   // contribution of chunk p to row p+1: A, B add, D sub
+    __shared__ double red[4][PMAX][SYS];   // reduced rows (A, B, C, D) during cyclic reduction
     __shared__ double xs[PMAX + 1][SYS];
+    __shared__ double c_alpha[NRMAX], c_VR[NRMAX], c_V[NRMAX];
 
-    const int nr = cf.nr;
+    const int nr = tab.nr;
+    for (int i = threadIdx.x; i < nr; i += THREADS) {
+        c_alpha[i] = tab.alpha[i];
+        c_VR[i] = tab.VR[i];
+        c_V[i] = tab.V[i];
+    }
     const int t = threadIdx.x;
     const int sl = t % SYS, p = t / SYS;
     const int nsys = nphi * nth;
@@ -66,14 +96,21 @@ __global__ __launch_bounds__(1024) void k_radial_part(double* __restrict__ Y, co
     const bool last = p == P - 1;
     double* col = Y + size_t(q) * nr * nth + l;
 
+    // this lane's rows, loaded unconditionally (row index clamped; values of
+    // rows beyond the chunk are never used) so that all loads are in flight
     double d[CH];
     double invw[CH];
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-        d[k] = 0.0;
+        const int row = s0 + k < nr ? s0 + k : nr - 1;
+        d[k] = col[size_t(row) * nth];
         invw[k] = 0.0;
-        if (active && k <= n) d[k] = cf.V[s0 + k] * col[size_t(s0 + k) * nth];
     }
+    __syncthreads();   // coefficient tables in LDS
+    const RowCoef cf{c_alpha, c_VR, nr};
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
+        if (k <= n) d[k] *= c_V[s0 + k];
 
     // ---- pass 1: eliminate the interior in both directions
     double Yf = 0.0, Uf = 0.0, Vf = 1.0, Yl = 0.0, Ul = 1.0, Vl = 0.0;
@@ -97,7 +134,7 @@ __global__ __launch_bounds__(1024) void k_radial_part(double* __restrict__ Y, co
                     zf = d[k] - mult * zf;
                     uf = -mult * uf;
                 }
-                invw[k] = 1.0 / w;
+                invw[k] = recip(w);
                 iwn = invw[k];
             }
         }
@@ -121,7 +158,7 @@ __global__ __launch_bounds__(1024) void k_radial_part(double* __restrict__ Y, co
                     zh = d[k] - mult * zh;
                     vh = -mult * vh;
                 }
-                iwh = 1.0 / wh;
+                iwh = recip(wh);
             }
         }
         Yf = zh * iwh;
@@ -140,31 +177,50 @@ __global__ __launch_bounds__(1024) void k_radial_part(double* __restrict__ Y, co
         nxt[2][p][sl] = oR * Yl;
     }
     __syncthreads();
-    if (t < SYS) {
-        // Thomas over the P separator rows of system sl,
-        //   A_r x_{r-1} + B_r x_r + C_r x_{r+1} = D_r;
-        // the eliminated C'_r, D'_r overwrite own[1][r], own[2][r].
-        double cp = 0.0, dp = 0.0;
-        for (int r = 0; r < P; ++r) {
-            double B = own[0][r][sl], D = own[2][r][sl];
-            const double C = own[1][r][sl];
-            if (r > 0) {
-                const double A = nxt[0][r - 1][sl];
-                B += nxt[1][r - 1][sl] - A * cp;
-                D -= nxt[2][r - 1][sl] + A * dp;
-            }
-            const double ib = 1.0 / B;
-            cp = C * ib;
-            dp = D * ib;
-            own[1][r][sl] = cp;
-            own[2][r][sl] = dp;
-        }
-        double x = 0.0;
-        for (int r = P - 1; r >= 0; --r) {
-            x = own[2][r][sl] - own[1][r][sl] * x;
-            xs[r][sl] = x;
+    // row p of the reduced system, A x_{p-1} + B x_p + C x_{p+1} = D
+    double rA = 0.0, rB = 1.0, rC = 0.0, rD = 0.0;
+    if (active) {
+        rB = own[0][p][sl];
+        rC = own[1][p][sl];
+        rD = own[2][p][sl];
+        if (p > 0) {
+            rA = nxt[0][p - 1][sl];
+            rB += nxt[1][p - 1][sl];
+            rD -= nxt[2][p - 1][sl];
         }
     }
+    // parallel cyclic reduction: after step h every row couples only to rows
+    // 2h away; rows outside 0..P-1 are absent (identity rows).
+    for (int h = 1; h < P; h *= 2) {
+        if (active) {
+            red[0][p][sl] = rA;
+            red[1][p][sl] = rB;
+            red[2][p][sl] = rC;
+            red[3][p][sl] = rD;
+        }
+        __syncthreads();
+        if (active) {
+            double a = 0.0, c = 0.0, nb = rB, nd = rD, na = 0.0, nc = 0.0;
+            if (p >= h) {
+                a = -rA * recip(red[1][p - h][sl]);
+                na = a * red[0][p - h][sl];
+                nb += a * red[2][p - h][sl];
+                nd += a * red[3][p - h][sl];
+            }
+            if (p + h < P) {
+                c = -rC * recip(red[1][p + h][sl]);
+                nc = c * red[2][p + h][sl];
+                nb += c * red[0][p + h][sl];
+                nd += c * red[3][p + h][sl];
+            }
+            rA = na;
+            rB = nb;
+            rC = nc;
+            rD = nd;
+        }
+        __syncthreads();
+    }
+    if (active) xs[p][sl] = rD * recip(rB);
     __syncthreads();
 
     // ---- pass 2: interior with both separators known

@@ -21,112 +21,158 @@
 namespace {
 
 // ------------------------------------------------------------------ FFT
+// Persistent workgroups: each one loops over blocks of JB lines and keeps the
+// global loads of its next block in flight (in registers) while the current
+// block is transformed in LDS.
 template <int N>
 __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
-                                                  const c64* __restrict__ tw, double scale, int nlines)
+                                                  const c64* __restrict__ tw_g, double scale, int nlines,
+                                                  int nblocks)
 {
     using S = FftShape<N>;
-    constexpr int N2 = S::N2, T = S::T, JB = S::JB;
-    __shared__ c64 lds[JB * N2];
-    const int L0 = blockIdx.x * JB;
-    const int nl = min(JB, nlines - L0);
+    constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
+    constexpr int PER = JB * N2 / 256;           // complex values loaded per thread and block
+    __shared__ c64 lds[JB * LS];
+    __shared__ c64 tws[N];
+    for (int t = threadIdx.x; t < N; t += 256) tws[t] = tw_g[t];
 
-    // contiguous lines -> LDS (a real line of N doubles is N2 complex values)
-    const double2* src = reinterpret_cast<const double2*>(rho + size_t(L0) * N);
-    for (int e = threadIdx.x; e < JB * N2; e += 256) {
-        double2 v = {0.0, 0.0};
-        if (e < nl * N2) v = src[e];
-        lds[e] = {v.x * scale, v.y * scale};
-    }
-    __syncthreads();
+    // a real line of N doubles is read as N2 complex values; indices past the
+    // end are clamped (those lines are never stored)
+    const double2* src = reinterpret_cast<const double2*>(rho);
+    const size_t total = size_t(nlines) * N2;
+    double2 pre[PER];
+    auto prefetch = [&](int blk) {
+        const size_t base = size_t(blk) * JB * N2 + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const size_t e = base + 256 * u;
+            pre[u] = src[e < total ? e : total - 1];
+        }
+    };
 
     const int line = threadIdx.x / T, tid = threadIdx.x % T;
-    fft_passes<N2, 1, T, S::E>(lds + line * N2, tid, tw);
-
-    // split Z into the half spectrum X_m and store halfcomplex planes
     const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
-    if (l < nl) {
-        const c64* Z = lds + l * N2;
-        const size_t plane = size_t(nlines);
-        double* out = X + L0 + l;
-        for (int p = grp; p <= N2 / 2; p += T) {
-            const c64 a = Z[p];
-            const c64 b = Z[(N2 - p) & (N2 - 1)];
-            // X_p = (a + conj b)/2 + w^p (a - conj b)/(2i)
-            const c64 A = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
-            const c64 B = {0.5 * (a.y + b.y), -0.5 * (a.x - b.x)};
-            const c64 w = tw[p];
-            const c64 Xp = cadd(A, cmul(w, B));
-            // partner X_{N2-p} = conj(A) - conj(w) * conj-swapped B
-            const c64 A2 = cconj(A);
-            const c64 B2 = {B.x, -B.y};
-            const c64 Xq = csub(A2, cmul(cconj(w), B2));
-            if (p == 0) {
-                out[0] = Xp.x;                         // Re X_0
-                out[size_t(N2) * plane] = Xq.x;        // Re X_{N/2}
-            } else if (2 * p == N2) {
-                out[size_t(p) * plane] = Xp.x;
-                out[size_t(N - p) * plane] = Xp.y;
-            } else {
-                out[size_t(p) * plane] = Xp.x;
-                out[size_t(N - p) * plane] = Xp.y;
-                out[size_t(N2 - p) * plane] = Xq.x;
-                out[size_t(N2 + p) * plane] = Xq.y;
+    const size_t plane = size_t(nlines);
+    int blk = blockIdx.x;
+    if (blk < nblocks) prefetch(blk);
+    for (; blk < nblocks; blk += gridDim.x) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            lds[(e / N2) * LS + pidx(e % N2)] = {pre[u].x * scale, pre[u].y * scale};
+        }
+        __syncthreads();
+        if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
+        fft_passes<N2, 1, T, S::E>(lds + line * LS, tid, tws);
+
+        // split Z into the half spectrum X_m and store halfcomplex planes
+        const int L0 = blk * JB;
+        const int nl = min(JB, nlines - L0);
+        if (l < nl) {
+            const c64* Z = lds + l * LS;
+            double* out = X + L0 + l;
+            for (int p = grp; p <= N2 / 2; p += T) {
+                const c64 a = Z[pidx(p)];
+                const c64 b = Z[pidx((N2 - p) & (N2 - 1))];
+                // X_p = (a + conj b)/2 + w^p (a - conj b)/(2i)
+                const c64 A = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+                const c64 B = {0.5 * (a.y + b.y), -0.5 * (a.x - b.x)};
+                const c64 w = tws[p];
+                const c64 Xp = cadd(A, cmul(w, B));
+                // partner X_{N2-p} = conj(A) - conj(w) conj(B)
+                const c64 Xq = csub(cconj(A), cmul(cconj(w), cconj(B)));
+                if (p == 0) {
+                    out[0] = Xp.x;                         // Re X_0
+                    out[size_t(N2) * plane] = Xq.x;        // Re X_{N/2}
+                } else if (2 * p == N2) {
+                    out[size_t(p) * plane] = Xp.x;
+                    out[size_t(N - p) * plane] = Xp.y;
+                } else {
+                    out[size_t(p) * plane] = Xp.x;
+                    out[size_t(N - p) * plane] = Xp.y;
+                    out[size_t(N2 - p) * plane] = Xq.x;
+                    out[size_t(N2 + p) * plane] = Xq.y;
+                }
             }
         }
+        __syncthreads();
     }
 }
 
 template <int N>
 __global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
-                                                  const c64* __restrict__ tw, int nlines)
+                                                  const c64* __restrict__ tw_g, int nlines, int nblocks)
 {
     using S = FftShape<N>;
-    constexpr int N2 = S::N2, T = S::T, JB = S::JB;
-    __shared__ c64 lds[JB * N2];
-    const int L0 = blockIdx.x * JB;
-    const int nl = min(JB, nlines - L0);
-
-    // rebuild Z_m = [X_m + conj X_{N2-m}] + i w^-m [X_m - conj X_{N2-m}] and
-    // store conj(Z): the inverse transform is conj(FFT(conj Z)).
-    const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
-    {
-        c64* Z = lds + l * N2;
-        const size_t plane = size_t(nlines);
-        const double* in = X + L0 + l;
-        const bool live = l < nl;
-        for (int p = grp; p <= N2 / 2; p += T) {
-            c64 xp, xq;   // X_p and X_{N2-p}
-            if (p == 0) {
-                xp = {live ? in[0] : 0.0, 0.0};
-                xq = {live ? in[size_t(N2) * plane] : 0.0, 0.0};
-            } else {
-                xp = {live ? in[size_t(p) * plane] : 0.0, live ? in[size_t(N - p) * plane] : 0.0};
-                xq = {live ? in[size_t(N2 - p) * plane] : 0.0, live ? in[size_t(N2 + p) * plane] : 0.0};
-            }
-            const c64 wc = cconj(tw[p]);               // w^-p
-            const c64 Ep = cadd(xp, cconj(xq)), Dp = csub(xp, cconj(xq));
-            const c64 iwD = cmul({-wc.y, wc.x}, Dp);   // i w^-p D
-            Z[p] = cconj(cadd(Ep, iwD));
-            if (p != 0 && 2 * p != N2) {
-                // Z_{N2-p} with w^-(N2-p) = -w^p
-                const c64 Eq = cadd(xq, cconj(xp)), Dq = csub(xq, cconj(xp));
-                const c64 w = tw[p];
-                const c64 iwDq = cmul({w.y, -w.x}, Dq);  // i * (-w^p) * Dq
-                Z[N2 - p] = cconj(cadd(Eq, iwDq));
-            }
-        }
-    }
-    __syncthreads();
+    constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
+    constexpr int NT = (N2 / 2 + T) / T;         // split tasks p = 0..N2/2 per thread
+    constexpr int PER = JB * N2 / 256;
+    __shared__ c64 lds[JB * LS];
+    __shared__ c64 tws[N];
+    for (int t = threadIdx.x; t < N; t += 256) tws[t] = tw_g[t];
 
     const int line = threadIdx.x / T, tid = threadIdx.x % T;
-    fft_passes<N2, 1, T, S::E>(lds + line * N2, tid, tw);
+    const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
+    const size_t plane = size_t(nlines);
 
-    // x_{2n} = Re z_n, x_{2n+1} = Im z_n with z = conj(FFT(conj Z))
-    double2* dst = reinterpret_cast<double2*>(phi + size_t(L0) * N);
-    for (int e = threadIdx.x; e < nl * N2; e += 256) {
-        const c64 v = lds[e];
-        dst[e] = double2{v.x, -v.y};
+    // raw halfcomplex values of task p: Re X_p, Im X_p, Re X_{N2-p}, Im X_{N2-p}
+    // (for p = 0 the imaginary slots hold Re X_0 and are discarded)
+    double pre[NT][4];
+    auto prefetch = [&](int blk) {
+        const int L = min(blk * JB + l, nlines - 1);
+        const double* in = X + L;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            int p = grp + T * u;
+            p = p <= N2 / 2 ? p : N2 / 2;
+            pre[u][0] = in[size_t(p) * plane];
+            pre[u][1] = in[size_t(p == 0 ? 0 : N - p) * plane];
+            pre[u][2] = in[size_t(N2 - p) * plane];
+            pre[u][3] = in[size_t(p == 0 ? 0 : N2 + p) * plane];
+        }
+    };
+
+    int blk = blockIdx.x;
+    if (blk < nblocks) prefetch(blk);
+    __syncthreads();   // twiddles
+    for (; blk < nblocks; blk += gridDim.x) {
+        // Z_m = [X_m + conj X_{N2-m}] + i w^-m [X_m - conj X_{N2-m}], stored as
+        // conj(Z): the inverse transform is conj(FFT(conj Z)).
+        c64* Z = lds + l * LS;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int p = grp + T * u;
+            if (p <= N2 / 2) {
+                const c64 xp = {pre[u][0], p == 0 ? 0.0 : pre[u][1]};
+                const c64 xq = {pre[u][2], p == 0 ? 0.0 : pre[u][3]};
+                const c64 wc = cconj(tws[p]);                 // w^-p
+                const c64 Ep = cadd(xp, cconj(xq)), Dp = csub(xp, cconj(xq));
+                Z[pidx(p)] = cconj(cadd(Ep, cmul({-wc.y, wc.x}, Dp)));
+                if (p != 0 && 2 * p != N2) {
+                    // Z_{N2-p} with w^-(N2-p) = -w^p
+                    const c64 Eq = cadd(xq, cconj(xp)), Dq = csub(xq, cconj(xp));
+                    const c64 w = tws[p];
+                    Z[pidx(N2 - p)] = cconj(cadd(Eq, cmul({w.y, -w.x}, Dq)));
+                }
+            }
+        }
+        __syncthreads();
+        if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
+        fft_passes<N2, 1, T, S::E>(lds + line * LS, tid, tws);
+
+        // x_{2n} = Re z_n, x_{2n+1} = Im z_n with z = conj(FFT(conj Z))
+        const int L0 = blk * JB;
+        const int nl = min(JB, nlines - L0);
+        double2* dst = reinterpret_cast<double2*>(phi + size_t(L0) * N);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < nl * N2) {
+                const c64 v = lds[(e / N2) * LS + pidx(e % N2)];
+                dst[e] = double2{v.x, -v.y};
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -253,6 +299,19 @@ __global__ __launch_bounds__(256) void k_radial(double* __restrict__ Y, double* 
     }
 }
 
+// Compute units of the current device (queried once).
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 // Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
 bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s)
 {
@@ -264,7 +323,7 @@ bool launch_proj(const double* A, const double* B, double* C, int M, int K, int 
     // one workgroup per CU at a time for the largest tile (B_m fills most of
     // the LDS): split the rows of a component only when there are fewer
     // components than CUs
-    int splits = (256 + nphi - 1) / nphi;
+    int splits = (device_cus() + nphi - 1) / nphi;
     const int maxsplits = (groups + proj::NWAVES - 1) / proj::NWAVES;
     if (splits > maxsplits) splits = maxsplits;
     if (splits < 1) splits = 1;
@@ -291,11 +350,12 @@ bool launch_proj(const double* A, const double* B, double* C, int M, int K, int 
 bool launch_radial_part(double* Y, const double* lam, const double* beta, const double* alpha, const double* V,
                         const double* VR, int nr, int nth, int nphi, hipStream_t s)
 {
+    if (nr > radial::NRMAX) return false;
     const int P = nr < radial::PMAX ? nr : radial::PMAX;
     const int ch = (nr + P - 1) / P;
     const radial::Coef cf{alpha, V, VR, nr};
     const int nsys = nphi * nth;
-    const dim3 grid((nsys + radial::SYS - 1) / radial::SYS), block(radial::SYS * radial::PMAX);
+    const dim3 grid((nsys + radial::SYS - 1) / radial::SYS), block(radial::THREADS);
 #define SPP_RADIAL_CASE(C)                                                                             \
     if (ch <= C) {                                                                                     \
         hipLaunchKernelGGL(radial::k_radial_part<C>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); \
@@ -315,11 +375,24 @@ void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw,
                      hipStream_t s)
 {
     using S = FftShape<N>;
-    const int blocks = (nlines + S::JB - 1) / S::JB;
+    const int nblocks = (nlines + S::JB - 1) / S::JB;
+    // persistent grid: as many workgroups as can be resident, blocks spread evenly
+    static int resident[2] = {0, 0};
+    int& res = resident[forward ? 0 : 1];
+    if (res == 0) {
+        int per_cu = 0;
+        if (forward)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_fwd<N>, 256, 0);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_inv<N>, 256, 0);
+        res = (per_cu > 0 ? per_cu : 1) * device_cus();
+    }
+    const int per = (nblocks + res - 1) / res;
+    const int grid = (nblocks + per - 1) / per;
     if (forward)
-        hipLaunchKernelGGL(k_rfft_fwd<N>, dim3(blocks), dim3(256), 0, s, in, out, tw, scale, nlines);
+        hipLaunchKernelGGL(k_rfft_fwd<N>, dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines, nblocks);
     else
-        hipLaunchKernelGGL(k_rfft_inv<N>, dim3(blocks), dim3(256), 0, s, in, out, tw, nlines);
+        hipLaunchKernelGGL(k_rfft_inv<N>, dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks);
 }
 
 bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
