@@ -24,6 +24,8 @@ struct spp_plan_layout {
     size_t alpha = 0;   // radial face coefficients, [N_r] (last entry 0)
     size_t V = 0;       // radial volume factors, [N_r]
     size_t VR = 0;      // V_i R_i, [N_r]
+    size_t Wimg = 0;    // LDS images of W_m for the projection kernel, [M][KMAX][NP]
+    size_t Himg = 0;    // LDS images of H_m, [M][KMAX][NP]
     size_t total = 0;
 };
 
@@ -31,7 +33,8 @@ struct spp_plan_s {
     int nr = 0, nth = 0, nphi = 0, nm = 0;   // nm = N_phi/2 + 1 azimuthal modes
     std::vector<double> r_if, th_if;
     // host tables (float64), layouts as in spp_plan_layout
-    std::vector<double> tw, W, H, lam, beta, alpha, V, VR;
+    std::vector<double> tw, W, H, lam, beta, alpha, V, VR, Wimg, Himg;
+    int proj_rn = 0;                           // tile width of the projection kernel (0: fallback)
     spp_plan_layout lay;
     size_t workspace_bytes = 0;
     void* dev = nullptr;                       // caller-owned device copy

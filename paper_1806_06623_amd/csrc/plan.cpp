@@ -10,6 +10,7 @@
 #include <thread>
 
 #include "internal.h"
+#include "proj_layout.h"
 
 static thread_local std::string g_last_error;
 
@@ -184,6 +185,23 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             return spp_fail(SPP_EDEVICE, "spp_plan_create: theta eigen iteration did not converge");
         }
 
+        // LDS images of W_m and H_m for the projection kernel (N_theta <= 128)
+        if (nth <= 128) {
+            const int rn = projimg::rn_for(nth);
+            const size_t ie = projimg::elems(rn);
+            const int NP = projimg::np(rn), KG = projimg::kpad(nth) / 4;
+            p->proj_rn = rn;
+            p->Wimg.assign(size_t(nm) * ie, 0.0);
+            p->Himg.assign(size_t(nm) * ie, 0.0);
+            for (int m = 0; m < nm; ++m)
+                for (int n = 0; n < nth; ++n)
+                    for (int k = 0; k < nth; ++k) {
+                        const size_t dst = size_t(m) * ie + size_t(projimg::row_of(k, KG)) * NP + n;
+                        p->Wimg[dst] = p->W[(size_t(m) * nth + n) * nth + k];
+                        p->Himg[dst] = p->H[(size_t(m) * nth + n) * nth + k];
+                    }
+        }
+
         // device layout
         spp_plan_layout& L = p->lay;
         size_t off = 0;
@@ -200,6 +218,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.alpha = take(p->alpha.size());
         L.V = take(p->V.size());
         L.VR = take(p->VR.size());
+        L.Wimg = take(p->Wimg.size());
+        L.Himg = take(p->Himg.size());
         L.total = off;
         const size_t field = spp_align256(size_t(nr) * nth * nphi * sizeof(double));
         p->workspace_bytes = 2 * field;
@@ -247,6 +267,8 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.alpha, p->alpha);
     put(p->lay.V, p->V);
     put(p->lay.VR, p->VR);
+    put(p->lay.Wimg, p->Wimg);
+    put(p->lay.Himg, p->Himg);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(plan_dev, img.data(), img.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

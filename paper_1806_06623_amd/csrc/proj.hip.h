@@ -5,7 +5,7 @@
 //   C[q][i][n] = sum_k A[q][i][k] * B[m(q)][n][k],   i < M (= N_r), n, k < K (= N_theta)
 //
 // One workgroup (8 waves) per (q, slice of rows).  The whole matrix B_m is
-// staged once in LDS; every wave then streams its own rows of A straight from
+// staged once in LDS (copied from an image the plan prepares in that layout); every wave then streams its own rows of A straight from
 // global memory into registers (double-buffered chunks of 8 k-steps) and
 // keeps a 16*RM x 16*RN block of C in accumulators.  The k index is permuted
 // between lanes so that both operands are contiguous per lane: in MFMA step s
@@ -18,14 +18,17 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "proj_layout.h"
+
 namespace proj {
 
 using d4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 
 template <int RN> struct Shape {
-    static constexpr int NMAX = 16 * RN;                    // largest N_theta handled
-    static constexpr int KMAX = (NMAX + 31) / 32 * 32;      // padded K capacity
-    static constexpr int NP = NMAX + 16;                    // padded LDS row length
+    static constexpr int NMAX = projimg::nmax(RN);          // largest N_theta handled
+    static constexpr int KMAX = projimg::kmax(RN);          // padded K capacity
+    static constexpr int NP = projimg::np(RN);              // padded LDS row length
+    static constexpr int ELEMS = KMAX * NP;                 // doubles per image
 };
 
 // Loads of A are unconditional: row and k indices are clamped into range and
@@ -64,25 +67,30 @@ template <int RN, int RM>
 __device__ __forceinline__ void mfma_chunk(d4 (&acc)[RM][RN], const double (&a)[RM][8], const double* __restrict__ Bs,
                                            int NP, int s0, int g, int lr)
 {
+    // B fragments of step u+1 are read from LDS before the MFMAs of step u
+    double b[2][RN];
+    const double* brow = Bs + (4 * s0 + g) * NP + lr;
+#pragma unroll
+    for (int cb = 0; cb < RN; ++cb) b[0][cb] = brow[cb * 16];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const double* brow = Bs + (4 * (s0 + u) + g) * NP + lr;
-        double b[RN];
+        if (u + 1 < 8) {
+            const double* bn = Bs + (4 * (s0 + u + 1) + g) * NP + lr;
 #pragma unroll
-        for (int cb = 0; cb < RN; ++cb) b[cb] = brow[cb * 16];
+            for (int cb = 0; cb < RN; ++cb) b[(u + 1) & 1][cb] = bn[cb * 16];
+        }
 #pragma unroll
         for (int rb = 0; rb < RM; ++rb)
 #pragma unroll
             for (int cb = 0; cb < RN; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][u], b[cb], acc[rb][cb], 0, 0, 0);
+                acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][u], b[u & 1][cb], acc[rb][cb], 0, 0, 0);
     }
 }
 
 constexpr int NWAVES = 8;                 // two waves per SIMD share one LDS copy of B_m
-constexpr int NTHREADS = 64 * NWAVES;
 
-template <int RN, int RM, bool KVEC>
-__global__ __launch_bounds__(NTHREADS) void k_proj_f64(const double* __restrict__ A, const double* __restrict__ B,
+template <int RN, int RM, bool KVEC, int NW = NWAVES>
+__global__ __launch_bounds__(64 * NW) void k_proj_f64(const double* __restrict__ A, const double* __restrict__ Bimg,
                                                   double* __restrict__ C, int M, int K, int nphi, int splits)
 {
     using S = Shape<RN>;
@@ -91,44 +99,43 @@ __global__ __launch_bounds__(NTHREADS) void k_proj_f64(const double* __restrict_
     const int q = blockIdx.y;
     const int m = q <= nphi / 2 ? q : nphi - q;
     const double* __restrict__ Aq = A + size_t(q) * M * K;
-    const double* __restrict__ Bm = B + size_t(m) * K * K;
     double* __restrict__ Cq = C + size_t(q) * M * K;
     const int Kp = (K + 31) & ~31;
     const int KG = Kp >> 2;
 
-    // ---- stage B_m in LDS (k-permuted rows, zero padding for k, n >= K).
-    // Each thread owns one column n and a strided set of k; eight loads are
-    // issued before their LDS stores.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int kb0 = g * KG;
+    double pa[RM][8], pb[RM][8];
+    // first A chunk of this wave's first row group: in flight during the staging
     {
-        constexpr int TPC = NTHREADS / S::NMAX;             // threads per column n
-        const int n = threadIdx.x % S::NMAX, part = threadIdx.x / S::NMAX;
-        const int nc = n < K ? n : K - 1;
-        const double* brow = Bm + size_t(nc) * K;
-        for (int kb = part; kb < Kp; kb += 8 * TPC) {
-            double v[8];
+        const int gi0 = blockIdx.x * NW + wave;
+        load_chunk<RM, KVEC>(pa, Aq, M, K, gi0 * 16 * RM < M ? gi0 * 16 * RM : 0, lr, kb0);
+    }
+
+    // ---- stage B_m: the plan holds it already in the LDS image layout
+    // (k-permuted, padded, zero-filled), so this is a contiguous copy
+    {
+        const double2* src = reinterpret_cast<const double2*>(Bimg + size_t(m) * S::ELEMS);
+        double2* dst = reinterpret_cast<double2*>(Bs);
+        constexpr int TH = 64 * NW, HALF = S::ELEMS / 2, PER = (HALF + TH - 1) / TH;
+        double2 v[PER];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = kb + u * TPC;
-                // multiply by a 0/1 mask (the matrix is finite) rather than
-                // select, so the load is issued unconditionally and all eight
-                // stay in flight together
-                const double keep = (n < K && k < K) ? 1.0 : 0.0;
-                v[u] = brow[k < K ? k : K - 1] * keep;
-            }
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TH;
+            v[u] = src[i < HALF ? i : HALF - 1];
+        }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = kb + u * TPC;
-                if (k < Kp) Bs[(4 * (k % KG) + k / KG) * S::NP + n] = v[u];
-            }
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TH;
+            if (i < HALF) dst[i] = v[u];
         }
     }
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lr = lane & 15, g = lane >> 4;
     const int ngroups = (M + 16 * RM - 1) / (16 * RM);
 
-    for (int gi = blockIdx.x * NWAVES + wave; gi < ngroups; gi += NWAVES * splits) {
+    for (int gi = blockIdx.x * NW + wave; gi < ngroups; gi += NW * splits) {
         const int rbase = gi * 16 * RM;
         d4 acc[RM][RN];
 #pragma unroll
@@ -136,9 +143,7 @@ __global__ __launch_bounds__(NTHREADS) void k_proj_f64(const double* __restrict_
 #pragma unroll
             for (int b = 0; b < RN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-        double pa[RM][8], pb[RM][8];
-        const int kb0 = g * KG;
-        load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0);
+        if (gi != blockIdx.x * NW + wave) load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0);
         for (int s0 = 0; s0 < KG; s0 += 16) {
             const int s1 = s0 + 8 < KG ? s0 + 8 : KG - 8;
             load_chunk<RM, KVEC>(pb, Aq, M, K, rbase, lr, kb0 + s1);

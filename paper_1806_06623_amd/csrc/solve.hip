@@ -315,9 +315,8 @@ int device_cus()
 // Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
 bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s)
 {
-    int rn = (K + 15) / 16;
-    if (rn > 8) return false;
-    rn = rn <= 1 ? 1 : rn <= 2 ? 2 : rn <= 4 ? 4 : 8;
+    if (K > 128) return false;
+    const int rn = projimg::rn_for(K);
     const int rm = rn == 8 ? 1 : rn == 4 ? 2 : 4;
     const int groups = (M + 16 * rm - 1) / (16 * rm);
     // one workgroup per CU at a time for the largest tile (B_m fills most of
@@ -327,7 +326,7 @@ bool launch_proj(const double* A, const double* B, double* C, int M, int K, int 
     const int maxsplits = (groups + proj::NWAVES - 1) / proj::NWAVES;
     if (splits > maxsplits) splits = maxsplits;
     if (splits < 1) splits = 1;
-    const dim3 grid(splits, nphi), block(proj::NTHREADS);
+    const dim3 grid(splits, nphi), block(64 * proj::NWAVES);
     const bool kvec = (K % 32) == 0;
 #define SPP_PROJ_CASE(RN, RM)                                                                              \
     case RN:                                                                                               \
@@ -431,6 +430,8 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
     const double* alpha = reinterpret_cast<const double*>(base + p->lay.alpha);
     const double* V = reinterpret_cast<const double*>(base + p->lay.V);
     const double* VR = reinterpret_cast<const double*>(base + p->lay.VR);
+    const double* Wimg = reinterpret_cast<const double*>(base + p->lay.Wimg);
+    const double* Himg = reinterpret_cast<const double*>(base + p->lay.Himg);
 
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
     const int nlines = nr * nth;
@@ -448,7 +449,7 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
     mark(1);
     const dim3 pgrid((nth + PBN - 1) / PBN, (nr + PBM - 1) / PBM, nphi);
-    if (!launch_proj(X, W, Y, nr, nth, nphi, s))
+    if (!launch_proj(X, Wimg, Y, nr, nth, nphi, s))
         hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
     mark(2);
     const int nsys = nphi * nth;
@@ -456,7 +457,7 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR,
                            nr, nth, nphi);
     mark(3);
-    if (!launch_proj(Y, H, X, nr, nth, nphi, s))
+    if (!launch_proj(Y, Himg, X, nr, nth, nphi, s))
         hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
     mark(4);
     launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s);
