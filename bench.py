@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--n-refine", type=int, default=1)
     ap.add_argument("--nr", type=int, default=550)
     ap.add_argument("--nth", type=int, default=128)
     ap.add_argument("--nphi", type=int, default=256)
@@ -121,6 +123,7 @@ def main():
 
     rho = torch.from_numpy(case["rho"]).to("cuda:0")
     phi = torch.empty_like(rho)
+    phi_m = torch.empty_like(rho)
     for _ in range(args.warmup):
         plan.solve(rho, G=case["G"], out=phi)
     torch.cuda.synchronize()
@@ -167,6 +170,23 @@ def main():
                 "per_launch": f"2*N_r*N_theta^2*N_phi = {proj_flops:.4g} flop per launch "
                               f"(all N_phi real Fourier components), avg launch {proj_ms * 1e3:.1f} us"}
 
+    # mixed-precision form on the same workload (FP32-MFMA projections + FP64 refinement)
+    mixed = None
+    if not args.no_mixed:
+        for _ in range(args.warmup):
+            plan.solve_mixed(rho, G=case["G"], n_refine=args.n_refine, out=phi_m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            plan.solve_mixed(rho, G=case["G"], n_refine=args.n_refine, out=phi_m)
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - t0
+        d = (phi_m - phi).abs().max().item() / phi.abs().max().item()
+        mixed = {"precision": "mixed_fp32", "n_refine": args.n_refine, "solves_per_s": round(K / el_m, 2),
+                 "gzones_per_s": round(zones * K / el_m / 1e9, 3), "ms_per_step": round(el_m * 1e3 / K, 4),
+                 "max_rel_diff_vs_fp64_gpu": d, "speedup_vs_fp64": round(elapsed / el_m, 3)}
+        log(f"mixed: {el_m * 1e3 / K:.3f} ms/solve, diff vs FP64 {d:.2e}")
+
     phi_np = phi.cpu().numpy()
     result = {
         "metric": METRIC, "value": round(solves_s, 2), "unit": "solves/s", "n_gpus": 1,
@@ -181,6 +201,7 @@ def main():
         "setup_s": round(setup_s, 3),
         "stages": stages,
         "roofline": roofline,
+        "mixed": mixed,
     }
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(case, phi_np, args.cpu_seconds)

@@ -50,11 +50,10 @@ typedef enum {
 
 typedef enum {
     SPP_FP64 = 0,          /* all stages in float64                                */
-    SPP_MIXED_FP32 = 1,    /* theta projections as FP32 MFMA products, FP32 spectral
-                              storage; FP64 radial solves and FP64 residual
-                              refinement (reserved: returns SPP_ENOTSUP until built) */
-    SPP_MIXED_BF16X3 = 2   /* split-BF16 (hi*hi + hi*lo + lo*hi) projections; as
-                              above (reserved)                                      */
+    SPP_MIXED_FP32 = 1,    /* theta projections as FP32 MFMA products accumulated in
+                              FP32; FFTs, radial solves, residual and the
+                              accumulated solution in FP64 (spp_solve_mixed)       */
+    SPP_MIXED_BF16X3 = 2   /* split-BF16 projections: reserved, SPP_ENOTSUP        */
 } spp_precision;
 
 typedef struct spp_grid_s* spp_grid;   /* host geometry, immutable        */
@@ -122,6 +121,36 @@ spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream);
  */
 spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double G,
                      void* workspace_dev, void* stream);
+
+/*
+ * Workspace bytes of one solve in flight for a given precision (SPP_FP64: as
+ * spp_plan_device_bytes; SPP_MIXED_FP32: four fields plus one shell).
+ * Errors: SPP_EINVAL (NULL), SPP_ENOTSUP (precision not built).
+ */
+spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, size_t* bytes);
+
+/*
+ * Mixed-precision solve with iterative refinement (spec production
+ * form; the operator and its exact solution are those of spp_solve).
+ *   s~ = FFT(4 pi G rho) in FP64, once;
+ *   g  = H F^-1 H^-1 s~ with the theta projections (Sec. 3.2) as FP32 MFMA
+ *        products (FP32-rounded eigenvector matrices, FP32 accumulation) and
+ *        the radial solves in FP64;
+ *   n_refine times: r = s~ - L g with L the FP64 discrete Laplacian of each
+ *        Fourier component (local flux stencil of Sec. 3.1 plus the outer
+ *        boundary term of Sec. 3.2), then g += H F^-1 H^-1 r as above;
+ *   Phi = inverse FFT of g in FP64.
+ * Each FP32 pass has a relative error near 1e-7; one refinement brings the
+ * result to the FP64 solution within ~1e-12 on the workloads tested.
+ *   prec           SPP_MIXED_FP32 (SPP_FP64 runs spp_solve);
+ *   n_refine       0..16 refinement steps;
+ *   workspace_dev  spp_plan_workspace_bytes(p, prec) bytes, 256-byte aligned;
+ * other arguments as spp_solve.  Needs N_theta <= 128 (SPP_ENOTSUP otherwise).
+ * Errors: as spp_solve, plus SPP_EINVAL for n_refine out of range and
+ * SPP_ENOTSUP for an unsupported precision.
+ */
+spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const double* rho_dev,
+                           double* phi_dev, double G, void* workspace_dev, void* stream);
 
 /*
  * spp_solve with per-stage timing, for benchmarks and profiling.  Records

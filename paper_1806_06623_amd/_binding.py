@@ -37,6 +37,10 @@ lib.spp_solve.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp]
 lib.spp_solve.restype = _c_int
 lib.spp_solve_profiled.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp, _dp]
 lib.spp_solve_profiled.restype = _c_int
+lib.spp_plan_workspace_bytes.argtypes = [_vp, _c_int, ctypes.POINTER(_c_size_t)]
+lib.spp_plan_workspace_bytes.restype = _c_int
+lib.spp_solve_mixed.argtypes = [_vp, _c_int, _c_int, _vp, _vp, _c_double, _vp, _vp]
+lib.spp_solve_mixed.restype = _c_int
 lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
 lib.spp_theta_eigensystem.restype = _c_int
 lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
@@ -125,6 +129,30 @@ class Plan:
         ws = self.workspace if workspace is None else workspace
         _check(lib.spp_solve(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
                              _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_solve")
+        return out
+
+    def workspace_bytes_for(self, precision):
+        b = _c_size_t()
+        _check(lib.spp_plan_workspace_bytes(self._plan, precision_codes[precision], ctypes.byref(b)),
+               "spp_plan_workspace_bytes")
+        return b.value
+
+    def solve_mixed(self, rho, G=1.0, precision="mixed_fp32", n_refine=1, out=None, workspace=None,
+                    stream=None):
+        """Mixed-precision solve with FP64 refinement (see spp_solve_mixed)."""
+        import torch
+        if rho.dtype != torch.float64 or not rho.is_contiguous() or tuple(rho.shape) != self.shape:
+            raise ValueError(f"rho must be a contiguous float64 tensor of shape {self.shape}")
+        if out is None:
+            out = torch.empty_like(rho)
+        if workspace is None:
+            need = self.workspace_bytes_for(precision)
+            if getattr(self, "_mixed_ws", None) is None or self._mixed_ws.numel() < need:
+                self._mixed_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            workspace = self._mixed_ws
+        _check(lib.spp_solve_mixed(self._plan, precision_codes[precision], int(n_refine), _vp(rho.data_ptr()),
+                                   _vp(out.data_ptr()), float(G), _vp(workspace.data_ptr()),
+                                   _stream_ptr(stream)), "spp_solve_mixed")
         return out
 
     def solve_profiled(self, rho, out, G=1.0, stream=None):

@@ -26,6 +26,12 @@ struct spp_plan_layout {
     size_t VR = 0;      // V_i R_i, [N_r]
     size_t Wimg = 0;    // LDS images of W_m for the projection kernel, [M][KMAX][NP]
     size_t Himg = 0;    // LDS images of H_m, [M][KMAX][NP]
+    size_t Wimg32 = 0;  // FP32 copies of the images (mixed-precision projections)
+    size_t Himg32 = 0;
+    size_t sig = 0;     // theta face coefficients sigma_{j+1/2}, [N_theta + 1] (poles 0)
+    size_t dmu = 0;     // cos theta_{j-1/2} - cos theta_{j+1/2}, [N_theta]
+    size_t Sj = 0;      // S_j, [N_theta]
+    size_t lamphi = 0;  // lambda_{phi,m}, [M]
     size_t total = 0;
 };
 
@@ -33,7 +39,8 @@ struct spp_plan_s {
     int nr = 0, nth = 0, nphi = 0, nm = 0;   // nm = N_phi/2 + 1 azimuthal modes
     std::vector<double> r_if, th_if;
     // host tables (float64), layouts as in spp_plan_layout
-    std::vector<double> tw, W, H, lam, beta, alpha, V, VR, Wimg, Himg;
+    std::vector<double> tw, W, H, lam, beta, alpha, V, VR, Wimg, Himg, sig, dmu, Sj, lamphi;
+    std::vector<float> Wimg32, Himg32;
     int proj_rn = 0;                           // tile width of the projection kernel (0: fallback)
     spp_plan_layout lay;
     size_t workspace_bytes = 0;
@@ -50,6 +57,13 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
 
 // Number of timed stages of one solve and their names.
 constexpr int SPP_NUM_STAGES = 5;
+
+// Device entry of the mixed-precision solve (solve.hip).
+spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision prec, int n_refine, const double* rho,
+                                  double* phi, double G, void* ws, void* stream);
+
+// Workspace of the mixed-precision solve: four fields and one outer shell.
+size_t spp_mixed_workspace_bytes(const spp_plan_s* p);
 
 // Symmetric tridiagonal eigensolver (eigen_ql.cpp): d[n] diagonal,
 // e[n-1] off-diagonal; on return d holds the eigenvalues in ascending order

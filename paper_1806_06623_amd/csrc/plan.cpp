@@ -185,6 +185,17 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             return spp_fail(SPP_EDEVICE, "spp_plan_create: theta eigen iteration did not converge");
         }
 
+        // theta and phi tables of the spectral residual (mixed-precision refinement)
+        p->sig = G.sigma;
+        p->dmu = G.dmu;
+        p->Sj.resize(nth);
+        for (int j = 0; j < nth; ++j) p->Sj[j] = G.dth[j] / (std::sin(G.th[j]) * G.dmu[j]);
+        p->lamphi.resize(nm);
+        for (int m = 0; m < nm; ++m) {
+            const double sm = std::sin(0.5 * m * dphi) / (0.5 * dphi);
+            p->lamphi[m] = -sm * sm;
+        }
+
         // LDS images of W_m and H_m for the projection kernel (N_theta <= 128)
         if (nth <= 128) {
             const int rn = projimg::rn_for(nth);
@@ -200,6 +211,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
                         p->Wimg[dst] = p->W[(size_t(m) * nth + n) * nth + k];
                         p->Himg[dst] = p->H[(size_t(m) * nth + n) * nth + k];
                     }
+            p->Wimg32.assign(p->Wimg.begin(), p->Wimg.end());
+            p->Himg32.assign(p->Himg.begin(), p->Himg.end());
         }
 
         // device layout
@@ -208,6 +221,11 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         auto take = [&](size_t n_doubles) {
             const size_t o = off;
             off = spp_align256(off + n_doubles * sizeof(double));
+            return o;
+        };
+        auto take_f = [&](size_t n_floats) {
+            const size_t o = off;
+            off = spp_align256(off + n_floats * sizeof(float));
             return o;
         };
         L.tw = take(p->tw.size());
@@ -220,6 +238,12 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.VR = take(p->VR.size());
         L.Wimg = take(p->Wimg.size());
         L.Himg = take(p->Himg.size());
+        L.Wimg32 = take_f(p->Wimg32.size());
+        L.Himg32 = take_f(p->Himg32.size());
+        L.sig = take(p->sig.size());
+        L.dmu = take(p->dmu.size());
+        L.Sj = take(p->Sj.size());
+        L.lamphi = take(p->lamphi.size());
         L.total = off;
         const size_t field = spp_align256(size_t(nr) * nth * nphi * sizeof(double));
         p->workspace_bytes = 2 * field;
@@ -269,6 +293,12 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.VR, p->VR);
     put(p->lay.Wimg, p->Wimg);
     put(p->lay.Himg, p->Himg);
+    std::memcpy(img.data() + p->lay.Wimg32, p->Wimg32.data(), p->Wimg32.size() * sizeof(float));
+    std::memcpy(img.data() + p->lay.Himg32, p->Himg32.data(), p->Himg32.size() * sizeof(float));
+    put(p->lay.sig, p->sig);
+    put(p->lay.dmu, p->dmu);
+    put(p->lay.Sj, p->Sj);
+    put(p->lay.lamphi, p->lamphi);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(plan_dev, img.data(), img.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -309,6 +339,27 @@ extern "C" spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_d
     const spp_status st = validate_solve("spp_solve", p, rho_dev, phi_dev, G, workspace_dev);
     if (st != SPP_OK) return st;
     return spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream);
+}
+
+extern "C" spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, size_t* bytes)
+{
+    if (!p || !bytes) return spp_fail(SPP_EINVAL, "spp_plan_workspace_bytes: NULL pointer");
+    if (prec == SPP_FP64) *bytes = p->workspace_bytes;
+    else if (prec == SPP_MIXED_FP32) *bytes = spp_mixed_workspace_bytes(p);
+    else return spp_fail(SPP_ENOTSUP, "spp_plan_workspace_bytes: precision not supported");
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const double* rho_dev,
+                                      double* phi_dev, double G, void* workspace_dev, void* stream)
+{
+    const spp_status st = validate_solve("spp_solve_mixed", p, rho_dev, phi_dev, G, workspace_dev);
+    if (st != SPP_OK) return st;
+    if (prec == SPP_FP64) return spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream);
+    if (prec != SPP_MIXED_FP32) return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: precision not supported");
+    if (n_refine < 0 || n_refine > 16) return spp_fail(SPP_EINVAL, "spp_solve_mixed: n_refine must be in [0, 16]");
+    if (p->proj_rn == 0) return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: needs N_theta <= 128");
+    return spp_launch_solve_mixed(p, prec, n_refine, rho_dev, phi_dev, G, workspace_dev, stream);
 }
 
 extern "C" spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev, double G,

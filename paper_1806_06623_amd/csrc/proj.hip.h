@@ -167,4 +167,114 @@ __global__ __launch_bounds__(64 * NW) void k_proj_f64(const double* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 variant for the mixed-precision solve: the same tiling, with A rounded
+// to float in registers, B_m taken from an FP32 image of the same layout, and
+// v_mfma_f32_16x16x4f32 products accumulated in FP32.  Its result register v
+// of lane l is C[4 (l / 16) + v][l % 16].  With ACCUM the result is added to C
+// (FP64) instead of overwriting it.
+using f4 = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+
+template <int RN, int RM>
+__device__ __forceinline__ void mfma_chunk_f32(f4 (&acc)[RM][RN], const double (&a)[RM][8], const float* __restrict__ Bs,
+                                               int NP, int s0, int g, int lr)
+{
+    float b[2][RN];
+    const float* brow = Bs + (4 * s0 + g) * NP + lr;
+#pragma unroll
+    for (int cb = 0; cb < RN; ++cb) b[0][cb] = brow[cb * 16];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (u + 1 < 8) {
+            const float* bn = Bs + (4 * (s0 + u + 1) + g) * NP + lr;
+#pragma unroll
+            for (int cb = 0; cb < RN; ++cb) b[(u + 1) & 1][cb] = bn[cb * 16];
+        }
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb) {
+            const float av = static_cast<float>(a[rb][u]);
+#pragma unroll
+            for (int cb = 0; cb < RN; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b[u & 1][cb], acc[rb][cb], 0, 0, 0);
+        }
+    }
+}
+
+template <int RN, int RM, bool KVEC, bool ACCUM, int NW = NWAVES>
+__global__ __launch_bounds__(64 * NW) void k_proj_f32(const double* __restrict__ A, const float* __restrict__ Bimg,
+                                                      double* __restrict__ C, int M, int K, int nphi, int splits)
+{
+    using S = Shape<RN>;
+    __shared__ float Bs[S::KMAX * S::NP];
+
+    const int q = blockIdx.y;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const double* __restrict__ Aq = A + size_t(q) * M * K;
+    double* __restrict__ Cq = C + size_t(q) * M * K;
+    const int KG = ((K + 31) & ~31) >> 2;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int kb0 = g * KG;
+    double pa[RM][8], pb[RM][8];
+    {
+        const int gi0 = blockIdx.x * NW + wave;
+        load_chunk<RM, KVEC>(pa, Aq, M, K, gi0 * 16 * RM < M ? gi0 * 16 * RM : 0, lr, kb0);
+    }
+    {
+        // S::ELEMS is a multiple of 4 (KMAX is a multiple of 32)
+        const float4* src = reinterpret_cast<const float4*>(Bimg + size_t(m) * S::ELEMS);
+        float4* dst = reinterpret_cast<float4*>(Bs);
+        constexpr int TH = 64 * NW, QUART = S::ELEMS / 4, PER = (QUART + TH - 1) / TH;
+        float4 v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TH;
+            v[u] = src[i < QUART ? i : QUART - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TH;
+            if (i < QUART) dst[i] = v[u];
+        }
+    }
+    __syncthreads();
+
+    const int ngroups = (M + 16 * RM - 1) / (16 * RM);
+    for (int gi = blockIdx.x * NW + wave; gi < ngroups; gi += NW * splits) {
+        const int rbase = gi * 16 * RM;
+        f4 acc[RM][RN];
+#pragma unroll
+        for (int a = 0; a < RM; ++a)
+#pragma unroll
+            for (int b = 0; b < RN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+        if (gi != blockIdx.x * NW + wave) load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0);
+        for (int s0 = 0; s0 < KG; s0 += 16) {
+            const int s1 = s0 + 8 < KG ? s0 + 8 : KG - 8;
+            load_chunk<RM, KVEC>(pb, Aq, M, K, rbase, lr, kb0 + s1);
+            mfma_chunk_f32<RN, RM>(acc, pa, Bs, S::NP, s0, g, lr);
+            const int s2 = s0 + 16 < KG ? s0 + 16 : KG - 8;
+            load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0 + s2);
+            if (s0 + 8 < KG) mfma_chunk_f32<RN, RM>(acc, pb, Bs, S::NP, s0 + 8, g, lr);
+        }
+
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < RN; ++cb) {
+                const int col = cb * 16 + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rbase + rb * 16 + 4 * g + v;
+                    if (row < M && col < K) {
+                        double* c = Cq + size_t(row) * K + col;
+                        const double val = static_cast<double>(acc[rb][cb][v]);
+                        *c = ACCUM ? *c + val : val;
+                    }
+                }
+            }
+    }
+}
+
 }  // namespace proj

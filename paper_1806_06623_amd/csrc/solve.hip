@@ -10,6 +10,7 @@
 // mode m, see fft.hip.h); both parts of a mode share the eigensystem of m.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -415,6 +416,115 @@ bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64
     }
 }
 
+// ------------------------------------------------------------------ mixed precision: FP64 residual
+// The refinement works on the Fourier components: the phi operator is
+// diagonal there (eigenvalue lambda_{phi,m}), so the discrete Laplacian of
+// component q is a local operator in (i, j) plus, on the outermost shell, the
+// boundary term of Sec. 3.2, which acts per theta eigenmode.
+
+// ob[q][j] = (H_m diag(beta_m) H_m^-1 g_q[N_r - 1, :])_j, one workgroup per q.
+// With H^-1 = H^T D and H = diag(1/dmu) W^T both sums read the stored
+// matrices along contiguous rows across the threads:
+//   c_l  = beta_l sum_j H[j][l] dmu_j g_j,     ob_j = (1/dmu_j) sum_l W[l][j] c_l.
+__global__ __launch_bounds__(256) void k_outer_bc(const double* __restrict__ Gf, double* __restrict__ ob,
+                                                  const double* __restrict__ W, const double* __restrict__ H,
+                                                  const double* __restrict__ beta, const double* __restrict__ dmu,
+                                                  int nr, int nth, int nphi)
+{
+    extern __shared__ double sh[];   // [2][nth]: weighted shell values, then the coefficients
+    const int q = blockIdx.x;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const double* shell = Gf + (size_t(q) * nr + (nr - 1)) * nth;
+    double* gs = sh;
+    double* cs = sh + nth;
+    for (int j = threadIdx.x; j < nth; j += blockDim.x) gs[j] = shell[j] * dmu[j];
+    __syncthreads();
+    const double* Wm = W + size_t(m) * nth * nth;   // [l][j]
+    const double* Hm = H + size_t(m) * nth * nth;   // [j][l]
+    for (int l = threadIdx.x; l < nth; l += blockDim.x) {
+        double c = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < nth; ++j) c += Hm[size_t(j) * nth + l] * gs[j];
+        cs[l] = c * beta[m * nth + l];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nth; j += blockDim.x) {
+        double v = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < nth; ++l) v += Wm[size_t(l) * nth + j] * cs[l];
+        ob[size_t(q) * nth + j] = v / dmu[j];
+    }
+}
+
+// r = s~ - L_q g for every element (q, i, j), FP64.
+struct ResidualTables {
+    const double* alpha;   // [nr], alpha[nr-1] = 0
+    const double* V;       // [nr]
+    const double* VR;      // [nr]
+    const double* sig;     // [nth + 1]
+    const double* dmu;     // [nth]
+    const double* Sj;      // [nth]
+    const double* lamphi;  // [nphi/2 + 1]
+};
+
+// 256 consecutive elements of one component plane per workgroup (32-bit index
+// arithmetic only).
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ St, const double* __restrict__ Gf,
+                                                  const double* __restrict__ ob, double* __restrict__ R,
+                                                  ResidualTables t, int nr, int nth, int nphi)
+{
+    const int el = blockIdx.x * 256 + threadIdx.x;
+    if (el >= nr * nth) return;
+    const int q = blockIdx.y;
+    const int i = el / nth, j = el - i * nth;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const size_t e = size_t(q) * nr * nth + el;
+    const double g0 = Gf[e];
+    // radial fluxes through the faces i+1/2 and i-1/2 (outer face: boundary term)
+    double flux = 0.0;
+    if (i + 1 < nr) flux += t.alpha[i] * (Gf[e + nth] - g0);
+    else flux -= ob[size_t(q) * nth + j];
+    if (i > 0) flux -= t.alpha[i - 1] * (g0 - Gf[e - nth]);
+    const double Vi = t.V[i];
+    // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
+    double th = 0.0;
+    if (j + 1 < nth) th += t.sig[j + 1] * (Gf[e + 1] - g0);
+    if (j > 0) th -= t.sig[j] * (g0 - Gf[e - 1]);
+    const double Ri = t.VR[i] / Vi;
+    const double Lg = flux / Vi + Ri * (th / t.dmu[j] + t.Sj[j] * t.lamphi[m] * g0);
+    R[e] = St[e] - Lg;
+}
+
+bool launch_proj_f32(const double* A, const float* B, double* C, int M, int K, int nphi, bool accum, hipStream_t s)
+{
+    if (K > 128) return false;
+    const int rn = projimg::rn_for(K);
+    const int rm = rn == 8 ? 1 : rn == 4 ? 2 : 4;
+    const int groups = (M + 16 * rm - 1) / (16 * rm);
+    int splits = (device_cus() + nphi - 1) / nphi;
+    const int maxsplits = (groups + proj::NWAVES - 1) / proj::NWAVES;
+    if (splits > maxsplits) splits = maxsplits;
+    if (splits < 1) splits = 1;
+    const dim3 grid(splits, nphi), block(64 * proj::NWAVES);
+    const bool kvec = (K % 32) == 0;
+#define SPP_PROJ32(RN, RM, KV, AC) \
+    hipLaunchKernelGGL((proj::k_proj_f32<RN, RM, KV, AC>), grid, block, 0, s, A, B, C, M, K, nphi, splits)
+#define SPP_PROJ32_CASE(RN, RM)                                                    \
+    case RN:                                                                       \
+        if (kvec) { if (accum) SPP_PROJ32(RN, RM, true, true); else SPP_PROJ32(RN, RM, true, false); }     \
+        else { if (accum) SPP_PROJ32(RN, RM, false, true); else SPP_PROJ32(RN, RM, false, false); }        \
+        break;
+    switch (rn) {
+        SPP_PROJ32_CASE(1, 4)
+        SPP_PROJ32_CASE(2, 4)
+        SPP_PROJ32_CASE(4, 2)
+        SPP_PROJ32_CASE(8, 1)
+    }
+#undef SPP_PROJ32_CASE
+#undef SPP_PROJ32
+    return true;
+}
+
 }  // namespace
 
 spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* phi, double G, void* ws,
@@ -464,5 +574,65 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
     mark(5);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve: ") + hipGetErrorString(e));
+    return SPP_OK;
+}
+
+size_t spp_mixed_workspace_bytes(const spp_plan_s* p)
+{
+    const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
+    return 4 * field + spp_align256(size_t(p->nphi) * p->nth * sizeof(double));
+}
+
+// Mixed-precision solve (iterative refinement in Fourier space):
+//   s~ = FFT(4 pi G rho)                          FP64, once
+//   g  = H~ F^-1 W~ s~                            FP32-MFMA projections, FP64 radial
+//   repeat n_refine times:
+//     r = s~ - L g                                FP64 (local stencil + outer term)
+//     g += H~ F^-1 W~ r
+//   Phi = IFFT(g)                                 FP64, once
+spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refine, const double* rho,
+                                  double* phi, double G, void* ws, void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char* base = static_cast<const char*>(p->dev);
+    auto tab = [&](size_t off) { return reinterpret_cast<const double*>(base + off); };
+    const c64* tw = reinterpret_cast<const c64*>(base + p->lay.tw);
+    const float* W32 = reinterpret_cast<const float*>(base + p->lay.Wimg32);
+    const float* H32 = reinterpret_cast<const float*>(base + p->lay.Himg32);
+
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    const int nlines = nr * nth;
+    const size_t field = spp_align256(size_t(nlines) * nphi * sizeof(double));
+    char* w = static_cast<char*>(ws);
+    double* St = reinterpret_cast<double*>(w);              // s~ (kept for the residuals)
+    double* Gf = reinterpret_cast<double*>(w + field);      // accumulated g
+    double* Y = reinterpret_cast<double*>(w + 2 * field);   // residual
+    double* Z = reinterpret_cast<double*>(w + 3 * field);   // projections / radial solves
+    double* ob = reinterpret_cast<double*>(w + 4 * field);  // outer-shell boundary term
+
+    const ResidualTables rt{tab(p->lay.alpha), tab(p->lay.V), tab(p->lay.VR), tab(p->lay.sig), tab(p->lay.dmu),
+                            tab(p->lay.Sj), tab(p->lay.lamphi)};
+    const double scale = 4.0 * M_PI * G / nphi;
+    if (!launch_fft(nphi, true, rho, St, tw, scale, nlines, s))
+        return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: unsupported nphi");
+    for (int it = 0; it <= n_refine; ++it) {
+        const double* src = St;
+        if (it > 0) {
+            hipLaunchKernelGGL(k_outer_bc, dim3(nphi), dim3(256), 2 * nth * sizeof(double), s, Gf, ob,
+                               tab(p->lay.W), tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu), nr, nth, nphi);
+            hipLaunchKernelGGL(k_residual, dim3((nlines + 255) / 256, nphi), dim3(256), 0, s, St, Gf, ob, Y, rt,
+                               nr, nth, nphi);
+            src = Y;
+        }
+        launch_proj_f32(src, W32, Z, nr, nth, nphi, false, s);
+        if (!launch_radial_part(Z, tab(p->lay.lam), tab(p->lay.beta), tab(p->lay.alpha), tab(p->lay.V),
+                                tab(p->lay.VR), nr, nth, nphi, s))
+            hipLaunchKernelGGL(k_radial, dim3((nphi * nth + 255) / 256), dim3(256), 0, s, Z, Y, tab(p->lay.lam),
+                               tab(p->lay.beta), tab(p->lay.alpha), tab(p->lay.V), tab(p->lay.VR), nr, nth, nphi);
+        launch_proj_f32(Z, H32, Gf, nr, nth, nphi, it > 0, s);
+    }
+    launch_fft(nphi, false, Gf, phi, tw, 1.0, nlines, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve_mixed: ") + hipGetErrorString(e));
     return SPP_OK;
 }
