@@ -58,6 +58,7 @@ typedef enum {
 
 typedef struct spp_grid_s* spp_grid;   /* host geometry, immutable        */
 typedef struct spp_plan_s* spp_plan;   /* eigensystems + device layout    */
+typedef struct spp_batch_s* spp_batch; /* captured graph of many solves   */
 
 /*
  * Create a grid from cell interfaces (Sec. 3.1: r_{i+-1/2}, theta_{j+-1/2},
@@ -166,6 +167,40 @@ spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const d
  */
 spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev, double G,
                               void* workspace_dev, void* stream, double* stage_ms);
+
+/*
+ * Projection tile autotuner.  Times each candidate row tile of the FP64
+ * projection kernel on this plan's shape (N_theta, N_r), using workspace_dev
+ * (spp_plan_device_bytes) as scratch, and records the fastest; later solves
+ * of any plan with the same (N_theta, N_r) in this process use it.
+ * Synchronises `stream`.  *chosen_rows (may be NULL) receives the rows per
+ * wave tile.  Errors: SPP_EINVAL, SPP_ESTATE (not uploaded), SPP_EDEVICE.
+ */
+spp_status spp_autotune_projection(spp_plan p, void* workspace_dev, void* stream, int* chosen_rows);
+
+/*
+ * Batched FP64 solves (many right-hand sides, grids of uneven size; plans
+ * may be shared between entries).  Solve r is exactly spp_solve(plans[r],
+ * rho_dev[r], phi_dev[r], G[r], ...) -- the same kernels, so each result is
+ * bitwise the one of a lone solve.
+ *   spp_batch_workspace_bytes: bytes of the one workspace the batch needs
+ *     (the per-plan workspaces, each 256-byte aligned, back to back);
+ *   spp_batch_create: validates every entry, then captures all solves into
+ *     one HIP graph in which the solves are independent branches (up to 8
+ *     concurrent chains).  Device pointers are fixed at creation.  The host
+ *     arrays are copied; device buffers must outlive the batch;
+ *   spp_batch_launch: replays the graph on `stream` (asynchronous);
+ *   spp_solve_batched: create + launch + synchronise `stream` + destroy.
+ * Errors: SPP_EINVAL (bad sizes/pointers/alignment, overlapping rho/phi),
+ * SPP_ESTATE (plan not uploaded), SPP_EDEVICE (stream/graph calls).
+ */
+spp_status spp_batch_workspace_bytes(int n, const spp_plan* plans, size_t* bytes);
+spp_status spp_batch_create(int n, const spp_plan* plans, const double* const* rho_dev, double* const* phi_dev,
+                            const double* G, void* workspace_dev, spp_batch* out);
+spp_status spp_batch_launch(spp_batch b, void* stream);
+void spp_batch_destroy(spp_batch b);
+spp_status spp_solve_batched(int n, const spp_plan* plans, const double* const* rho_dev, double* const* phi_dev,
+                             const double* G, void* workspace_dev, void* stream);
 
 /*
  * Host copy of the theta eigensystem of mode m (0 <= m <= N_phi/2), for tests:

@@ -8,10 +8,11 @@ Importing this package fails loudly if the library has not been built
 """
 from ._binding import (  # noqa: F401
     LIB_PATH,
+    Batch,
     Plan,
     SphPoissonError,
     lib,
     precision_codes,
 )
 
-__all__ = ["Plan", "SphPoissonError", "lib", "LIB_PATH", "precision_codes"]
+__all__ = ["Batch", "Plan", "SphPoissonError", "lib", "LIB_PATH", "precision_codes"]

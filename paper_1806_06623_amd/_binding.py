@@ -41,6 +41,19 @@ lib.spp_plan_workspace_bytes.argtypes = [_vp, _c_int, ctypes.POINTER(_c_size_t)]
 lib.spp_plan_workspace_bytes.restype = _c_int
 lib.spp_solve_mixed.argtypes = [_vp, _c_int, _c_int, _vp, _vp, _c_double, _vp, _vp]
 lib.spp_solve_mixed.restype = _c_int
+lib.spp_autotune_projection.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_c_int)]
+lib.spp_autotune_projection.restype = _c_int
+_vpp = ctypes.POINTER(_vp)
+lib.spp_batch_workspace_bytes.argtypes = [_c_int, _vpp, ctypes.POINTER(_c_size_t)]
+lib.spp_batch_workspace_bytes.restype = _c_int
+lib.spp_batch_create.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _vp, ctypes.POINTER(_vp)]
+lib.spp_batch_create.restype = _c_int
+lib.spp_batch_launch.argtypes = [_vp, _vp]
+lib.spp_batch_launch.restype = _c_int
+lib.spp_batch_destroy.argtypes = [_vp]
+lib.spp_batch_destroy.restype = None
+lib.spp_solve_batched.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _vp, _vp]
+lib.spp_solve_batched.restype = _c_int
 lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
 lib.spp_theta_eigensystem.restype = _c_int
 lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
@@ -167,6 +180,13 @@ class Plan:
                                       st.ctypes.data_as(_dp)), "spp_solve_profiled")
         return st
 
+    def autotune(self, stream=None):
+        """Time the projection tile candidates for this shape; returns rows per wave tile."""
+        rows = _c_int()
+        _check(lib.spp_autotune_projection(self._plan, _vp(self.workspace.data_ptr()), _stream_ptr(stream),
+                                           ctypes.byref(rows)), "spp_autotune_projection")
+        return rows.value
+
     def theta_eigensystem(self, m):
         H = np.empty((self.nth, self.nth))
         lam = np.empty(self.nth)
@@ -179,3 +199,43 @@ class Plan:
         if p is not None and p.value:
             lib.spp_plan_destroy(p)
             self._plan = None
+
+
+class Batch:
+    """Many FP64 solves captured once into one HIP graph (see spp_batch_create).
+
+    ``plans[r]``, ``rhos[r]``, ``phis[r]`` and ``Gs[r]`` describe solve r; the
+    tensors are kept alive by the batch.  ``launch()`` replays all solves.
+    """
+
+    def __init__(self, plans, rhos, phis, Gs):
+        import torch
+        n = len(plans)
+        if not (len(rhos) == len(phis) == len(Gs) == n) or n == 0:
+            raise ValueError("plans, rhos, phis and Gs must have the same non-zero length")
+        for p, x, y in zip(plans, rhos, phis):
+            for t in (x, y):
+                if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != p.shape:
+                    raise ValueError(f"tensors must be contiguous float64 of shape {p.shape}")
+        self._keep = (list(plans), list(rhos), list(phis))
+        self.n = n
+        self._plans = (_vp * n)(*[p._plan for p in plans])
+        self._rho = (_vp * n)(*[x.data_ptr() for x in rhos])
+        self._phi = (_vp * n)(*[y.data_ptr() for y in phis])
+        self._G = (ctypes.c_double * n)(*[float(g) for g in Gs])
+        wb = _c_size_t()
+        _check(lib.spp_batch_workspace_bytes(n, self._plans, ctypes.byref(wb)), "spp_batch_workspace_bytes")
+        self.workspace = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=plans[0].device)
+        b = _vp()
+        _check(lib.spp_batch_create(n, self._plans, self._rho, self._phi, self._G,
+                                    _vp(self.workspace.data_ptr()), ctypes.byref(b)), "spp_batch_create")
+        self._batch = b
+
+    def launch(self, stream=None):
+        _check(lib.spp_batch_launch(self._batch, _stream_ptr(stream)), "spp_batch_launch")
+
+    def __del__(self):
+        b = getattr(self, "_batch", None)
+        if b is not None and b.value:
+            lib.spp_batch_destroy(b)
+            self._batch = None

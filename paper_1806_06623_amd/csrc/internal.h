@@ -65,6 +65,14 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision prec, int n
 // Workspace of the mixed-precision solve: four fields and one outer shell.
 size_t spp_mixed_workspace_bytes(const spp_plan_s* p);
 
+// Projection tile autotuner and launch-cache prewarm (solve.hip).
+spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* stream, int* chosen_rm);
+void spp_prewarm_launch_caches(const spp_plan_s* p);
+
+// Argument checks shared by the solve entry points (plan.cpp).
+spp_status spp_validate_solve(const char* who, const spp_plan_s* p, const double* rho_dev, const double* phi_dev,
+                              double G, const void* workspace_dev);
+
 // Symmetric tridiagonal eigensolver (eigen_ql.cpp): d[n] diagonal,
 // e[n-1] off-diagonal; on return d holds the eigenvalues in ascending order
 // and Z (row-major n x n) the orthonormal eigenvectors as columns.

@@ -318,8 +318,8 @@ extern "C" spp_status spp_theta_eigensystem(spp_plan p, int m, double* H, double
     return SPP_OK;
 }
 
-static spp_status validate_solve(const char* who, spp_plan p, const double* rho_dev, const double* phi_dev,
-                                 double G, const void* workspace_dev)
+spp_status spp_validate_solve(const char* who, const spp_plan_s* p, const double* rho_dev, const double* phi_dev,
+                              double G, const void* workspace_dev)
 {
     const std::string w(who);
     if (!p || !rho_dev || !phi_dev || !workspace_dev) return spp_fail(SPP_EINVAL, w + ": NULL pointer");
@@ -336,7 +336,7 @@ static spp_status validate_solve(const char* who, spp_plan p, const double* rho_
 extern "C" spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double G,
                                 void* workspace_dev, void* stream)
 {
-    const spp_status st = validate_solve("spp_solve", p, rho_dev, phi_dev, G, workspace_dev);
+    const spp_status st = spp_validate_solve("spp_solve", p, rho_dev, phi_dev, G, workspace_dev);
     if (st != SPP_OK) return st;
     return spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream);
 }
@@ -353,7 +353,7 @@ extern "C" spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, s
 extern "C" spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const double* rho_dev,
                                       double* phi_dev, double G, void* workspace_dev, void* stream)
 {
-    const spp_status st = validate_solve("spp_solve_mixed", p, rho_dev, phi_dev, G, workspace_dev);
+    const spp_status st = spp_validate_solve("spp_solve_mixed", p, rho_dev, phi_dev, G, workspace_dev);
     if (st != SPP_OK) return st;
     if (prec == SPP_FP64) return spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream);
     if (prec != SPP_MIXED_FP32) return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: precision not supported");
@@ -362,11 +362,21 @@ extern "C" spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refi
     return spp_launch_solve_mixed(p, prec, n_refine, rho_dev, phi_dev, G, workspace_dev, stream);
 }
 
+extern "C" spp_status spp_autotune_projection(spp_plan p, void* workspace_dev, void* stream, int* chosen_rows)
+{
+    if (!p || !workspace_dev) return spp_fail(SPP_EINVAL, "spp_autotune_projection: NULL pointer");
+    if (!p->dev) return spp_fail(SPP_ESTATE, "spp_autotune_projection: plan not uploaded");
+    int rm = 0;
+    const spp_status st = spp_autotune_projection_impl(p, workspace_dev, stream, &rm);
+    if (st == SPP_OK && chosen_rows) *chosen_rows = 16 * rm;
+    return st;
+}
+
 extern "C" spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev, double G,
                                          void* workspace_dev, void* stream, double* stage_ms)
 {
     if (!stage_ms) return spp_fail(SPP_EINVAL, "spp_solve_profiled: NULL stage_ms");
-    spp_status st = validate_solve("spp_solve_profiled", p, rho_dev, phi_dev, G, workspace_dev);
+    spp_status st = spp_validate_solve("spp_solve_profiled", p, rho_dev, phi_dev, G, workspace_dev);
     if (st != SPP_OK) return st;
     hipEvent_t ev[SPP_NUM_STAGES + 1] = {};
     int made = 0;

@@ -12,7 +12,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "fft.hip.h"
 #include "internal.h"
@@ -314,11 +317,35 @@ int device_cus()
 }
 
 // Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
-bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s)
+// Rows per wave tile (16 RM) of the projection kernel.  The default depends on
+// the tile width; spp_autotune_projection may record a measured choice per
+// (N_theta, N_r), which then takes precedence.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tuned_rm;
+
+int proj_rm_default(int rn) { return rn == 8 ? 1 : rn == 4 ? 2 : 4; }
+
+int proj_rm(int K, int M)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tuned_rm.find({K, M});
+    return it != g_tuned_rm.end() ? it->second : proj_rm_default(projimg::rn_for(K));
+}
+
+// Candidate RM values per tile width (each one an instantiated kernel).
+std::vector<int> proj_rm_candidates(int rn)
+{
+    switch (rn) {
+    case 8: return {1, 2};
+    case 4: return {1, 2, 4};
+    default: return {2, 4};
+    }
+}
+
+bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, int nphi, int rm, hipStream_t s)
 {
     if (K > 128) return false;
     const int rn = projimg::rn_for(K);
-    const int rm = rn == 8 ? 1 : rn == 4 ? 2 : 4;
     const int groups = (M + 16 * rm - 1) / (16 * rm);
     // one workgroup per CU at a time for the largest tile (B_m fills most of
     // the LDS): split the rows of a component only when there are fewer
@@ -329,21 +356,30 @@ bool launch_proj(const double* A, const double* B, double* C, int M, int K, int 
     if (splits < 1) splits = 1;
     const dim3 grid(splits, nphi), block(64 * proj::NWAVES);
     const bool kvec = (K % 32) == 0;
-#define SPP_PROJ_CASE(RN, RM)                                                                              \
-    case RN:                                                                                               \
-        if (kvec)                                                                                          \
+#define SPP_PROJ(RN, RM)                                                                                       \
+    do {                                                                                                       \
+        if (kvec)                                                                                              \
             hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, true>), grid, block, 0, s, A, B, C, M, K, nphi, splits);  \
-        else                                                                                               \
+        else                                                                                                   \
             hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, false>), grid, block, 0, s, A, B, C, M, K, nphi, splits); \
-        break;
-    switch (rn) {
-        SPP_PROJ_CASE(1, 4)
-        SPP_PROJ_CASE(2, 4)
-        SPP_PROJ_CASE(4, 2)
-        SPP_PROJ_CASE(8, 1)
+    } while (0)
+    if (rn == 8) {
+        if (rm == 2) SPP_PROJ(8, 2); else SPP_PROJ(8, 1);
+    } else if (rn == 4) {
+        if (rm == 1) SPP_PROJ(4, 1); else if (rm == 4) SPP_PROJ(4, 4); else SPP_PROJ(4, 2);
+    } else if (rn == 2) {
+        if (rm == 2) SPP_PROJ(2, 2); else SPP_PROJ(2, 4);
+    } else {
+        if (rm == 2) SPP_PROJ(1, 2); else SPP_PROJ(1, 4);
     }
-#undef SPP_PROJ_CASE
+#undef SPP_PROJ
     return true;
+}
+
+// Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
+bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s)
+{
+    return launch_proj_rm(A, B, C, M, K, nphi, K <= 128 ? proj_rm(K, M) : 0, s);
 }
 
 // Partitioned radial solve for N_r <= 32 * 20; returns false above that.
@@ -370,13 +406,10 @@ bool launch_radial_part(double* Y, const double* lam, const double* beta, const 
     return false;
 }
 
+// Workgroups of the FFT kernel for N that fit on the device at once (cached).
 template <int N>
-void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
-                     hipStream_t s)
+int fft_resident(bool forward)
 {
-    using S = FftShape<N>;
-    const int nblocks = (nlines + S::JB - 1) / S::JB;
-    // persistent grid: as many workgroups as can be resident, blocks spread evenly
     static int resident[2] = {0, 0};
     int& res = resident[forward ? 0 : 1];
     if (res == 0) {
@@ -387,6 +420,17 @@ void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw,
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_inv<N>, 256, 0);
         res = (per_cu > 0 ? per_cu : 1) * device_cus();
     }
+    return res;
+}
+
+template <int N>
+void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
+                     hipStream_t s)
+{
+    using S = FftShape<N>;
+    const int nblocks = (nlines + S::JB - 1) / S::JB;
+    // persistent grid: as many workgroups as can be resident, blocks spread evenly
+    const int res = fft_resident<N>(forward);
     const int per = (nblocks + res - 1) / res;
     const int grid = (nblocks + per - 1) / per;
     if (forward)
@@ -635,4 +679,67 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve_mixed: ") + hipGetErrorString(e));
     return SPP_OK;
+}
+
+// Time every candidate tile of the projection kernel on this plan's shape
+// (forward projection on the workspace buffers, whose contents do not matter
+// for timing) and record the fastest for (N_theta, N_r).  Synchronises the
+// stream.  *chosen_rm receives the choice (may be NULL).
+spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* stream, int* chosen_rm)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->nth > 128) {
+        if (chosen_rm) *chosen_rm = 0;
+        return SPP_OK;
+    }
+    const char* base = static_cast<const char*>(p->dev);
+    const double* Wimg = reinterpret_cast<const double*>(base + p->lay.Wimg);
+    const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
+    const double* A = static_cast<const double*>(ws);
+    double* C = reinterpret_cast<double*>(static_cast<char*>(ws) + field);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return spp_fail(SPP_EDEVICE, "autotune: hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return spp_fail(SPP_EDEVICE, "autotune: hipEventCreate");
+    }
+    int best = proj_rm_default(projimg::rn_for(p->nth));
+    float best_ms = 1e30f;
+    for (int rm : proj_rm_candidates(projimg::rn_for(p->nth))) {
+        launch_proj_rm(A, Wimg, C, p->nr, p->nth, p->nphi, rm, s);   // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 3; ++r) launch_proj_rm(A, Wimg, C, p->nr, p->nth, p->nphi, rm, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = rm;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned_rm[{p->nth, p->nr}] = best;
+    }
+    if (chosen_rm) *chosen_rm = best;
+    return SPP_OK;
+}
+
+// Evaluate the launch-configuration caches (CU count, FFT occupancy) for
+// this plan outside any stream capture.
+void spp_prewarm_launch_caches(const spp_plan_s* p)
+{
+    (void)device_cus();
+    switch (p->nphi) {
+#define SPP_WARM(n) case n: fft_resident<n>(true); fft_resident<n>(false); break;
+        SPP_WARM(4) SPP_WARM(8) SPP_WARM(16) SPP_WARM(32) SPP_WARM(64)
+        SPP_WARM(128) SPP_WARM(256) SPP_WARM(512) SPP_WARM(1024) SPP_WARM(2048)
+#undef SPP_WARM
+    default: break;
+    }
 }
