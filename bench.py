@@ -119,6 +119,60 @@ def batched_leg(spp, torch, synthetic, steps):
             "graph_speedup_vs_sequential": round(el_seq / el, 3)}
 
 
+def serving_leg(spp, torch, synthetic, n_requests, rates):
+    """Poisson arrivals (seed 4) of requests drawn uniformly from the grid
+    classes (128,32,64), (256,64,128), (550,128,256) with off-centre point
+    mass + Gaussian sources; plans resident, workspaces from an HBM pool,
+    8 concurrent slots.  First the saturated throughput (all requests queued
+    at once), then arrival rates at the given fractions of it."""
+    classes = synthetic.SERVING_CLASSES
+    plans, srcs, outs = [], [], []
+    for c in classes:
+        r_if, th_if, nphi = synthetic.stellar_grid(*c)
+        plans.append(spp.Plan(r_if, th_if, nphi, device="cuda:0"))
+        srcs.append([torch.from_numpy(synthetic.serving_source(r_if, th_if, nphi, seed=4000 + 10 * len(srcs) + k))
+                     .to("cuda:0") for k in range(4)])
+        outs.append([torch.empty_like(srcs[-1][0]) for _ in range(16)])
+    n_slots = 8
+    pool = n_slots * max(p.workspace_bytes for p in plans)
+    rng = np.random.default_rng(4)
+    cls_of = rng.integers(0, len(classes), size=n_requests)
+    gaps = rng.exponential(1.0, size=n_requests)
+    zones = [a * b * c for a, b, c in classes]
+
+    def run(rate):
+        srv = spp.Server(plans, pool_bytes=pool, n_slots=n_slots)
+        count = [0] * len(classes)
+        t0 = srv.now() + 0.01
+        arrivals = t0 + (np.cumsum(gaps) / rate if rate else np.zeros(n_requests))
+        for k in range(n_requests):
+            c = int(cls_of[k])
+            j = count[c]
+            count[c] += 1
+            srv.submit(c, srcs[c][j % 4], outs[c][j % 16], request_id=k, not_before=float(arrivals[k]))
+        srv.drain(300.0)
+        done = srv.poll(n_requests + 16)
+        srv.close()
+        lat = np.array([d["t_done"] - d["t_arrival"] for d in done]) * 1e3
+        span = max(d["t_done"] for d in done) - min(d["t_arrival"] for d in done)
+        z = sum(zones[d["plan_index"]] for d in done)
+        return {"offered_rate_per_s": None if not rate else round(rate, 1), "requests": len(done),
+                "solves_per_s": round(len(done) / span, 1), "gzones_per_s": round(z / span / 1e9, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4)}
+
+    run(None)   # warm-up
+    sat = run(None)
+    log(f"serving saturated: {sat['solves_per_s']} solves/s, p50 {sat['p50_ms']} ms, p99 {sat['p99_ms']} ms")
+    out = {"classes": [list(c) for c in classes], "n_slots": n_slots, "pool_bytes": pool,
+           "saturated": sat, "rates": []}
+    for f in rates:
+        r = run(f * sat["solves_per_s"])
+        r["fraction_of_saturation"] = f
+        out["rates"].append(r)
+        log(f"serving at {f:.2f} x sat: {r['solves_per_s']} solves/s, p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +184,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--n-refine", type=int, default=1)
     ap.add_argument("--nr", type=int, default=550)
     ap.add_argument("--nth", type=int, default=128)
@@ -235,6 +291,8 @@ def main():
         log(f"mixed: {el_m * 1e3 / K:.3f} ms/solve, diff vs FP64 {d:.2e}")
 
     batch = None if args.no_batch else batched_leg(spp, torch, synthetic, args.batch_steps)
+    serving = None if args.no_serving else serving_leg(spp, torch, synthetic, args.serving_requests,
+                                                        (0.5, 0.8, 0.95))
 
     phi_np = phi.cpu().numpy()
     result = {
@@ -252,6 +310,7 @@ def main():
         "roofline": roofline,
         "mixed": mixed,
         "batched": batch,
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(case, phi_np, args.cpu_seconds)

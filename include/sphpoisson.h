@@ -59,6 +59,26 @@ typedef enum {
 typedef struct spp_grid_s* spp_grid;   /* host geometry, immutable        */
 typedef struct spp_plan_s* spp_plan;   /* eigensystems + device layout    */
 typedef struct spp_batch_s* spp_batch; /* captured graph of many solves   */
+typedef struct spp_server_s* spp_server; /* serving loop                  */
+
+/* One request of the serving loop. */
+typedef struct {
+    int plan_index;          /* index into the server's plans (grid class)       */
+    const double* rho_dev;   /* device, [N_r][N_theta][N_phi] of that plan        */
+    double* phi_dev;         /* device, same shape, written                       */
+    double G;
+    long long request_id;    /* caller's tag, echoed in the completion            */
+} spp_request;
+
+/* Completion record; times in seconds on the server's steady clock. */
+typedef struct {
+    long long request_id;
+    int plan_index;
+    double t_arrival;        /* submission time or scheduled arrival, whichever is later */
+    double t_admit;          /* admitted: memory and a stream slot were free      */
+    double t_done;           /* completion observed by the scheduler              */
+    int status;              /* SPP_OK or the failure                             */
+} spp_completion;
 
 /*
  * Create a grid from cell interfaces (Sec. 3.1: r_{i+-1/2}, theta_{j+-1/2},
@@ -201,6 +221,35 @@ spp_status spp_batch_launch(spp_batch b, void* stream);
 void spp_batch_destroy(spp_batch b);
 spp_status spp_solve_batched(int n, const spp_plan* plans, const double* const* rho_dev, double* const* phi_dev,
                              const double* G, void* workspace_dev, void* stream);
+
+/*
+ * Serving loop with continuous batching (FP64 solves).
+ *   spp_server_create: plans[0..n_plans) are the resident grid classes
+ *     (uploaded; their eigenbases stay on the device); pool_dev/pool_bytes is
+ *     caller-owned device memory from which each admitted request takes its
+ *     workspace (HBM-footprint admission); n_slots (1..64) streams run
+ *     admitted solves concurrently.  Starts one scheduler thread.
+ *   spp_server_submit: thread-safe; queues *req to arrive at max(now,
+ *     not_before) (server clock, seconds; pass 0 for "now").  Requests are
+ *     admitted in arrival order when a slot is free and their workspace fits
+ *     in the pool.  SPP_ENOMEM if one request exceeds the whole pool.
+ *   spp_server_poll: moves up to max_out completion records to out (host);
+ *     *n_out receives the count.  Returns SPP_EDEVICE once a solve failed.
+ *   spp_server_drain: waits until every submitted request has completed
+ *     (SPP_ESTATE after timeout_s seconds).
+ *   spp_server_now: current server clock.
+ *   spp_server_destroy: drops queued requests, waits for running ones.
+ * Each request runs exactly the kernels of spp_solve, so its result is
+ * bitwise the same alone and in any mix.  rho/phi buffers must stay valid
+ * until the request's completion has been polled.
+ */
+spp_status spp_server_create(int n_plans, const spp_plan* plans, void* pool_dev, size_t pool_bytes, int n_slots,
+                             spp_server* out);
+spp_status spp_server_submit(spp_server s, const spp_request* req, double not_before);
+spp_status spp_server_poll(spp_server s, spp_completion* out, int max_out, int* n_out);
+spp_status spp_server_drain(spp_server s, double timeout_s);
+spp_status spp_server_now(spp_server s, double* t);
+void spp_server_destroy(spp_server s);
 
 /*
  * Host copy of the theta eigensystem of mode m (0 <= m <= N_phi/2), for tests:

@@ -10,9 +10,10 @@ from ._binding import (  # noqa: F401
     LIB_PATH,
     Batch,
     Plan,
+    Server,
     SphPoissonError,
     lib,
     precision_codes,
 )
 
-__all__ = ["Batch", "Plan", "SphPoissonError", "lib", "LIB_PATH", "precision_codes"]
+__all__ = ["Batch", "Plan", "Server", "SphPoissonError", "lib", "LIB_PATH", "precision_codes"]

@@ -54,6 +54,30 @@ lib.spp_batch_destroy.argtypes = [_vp]
 lib.spp_batch_destroy.restype = None
 lib.spp_solve_batched.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _vp, _vp]
 lib.spp_solve_batched.restype = _c_int
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("plan_index", _c_int), ("rho_dev", _vp), ("phi_dev", _vp), ("G", _c_double),
+                ("request_id", ctypes.c_longlong)]
+
+
+class _Completion(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_longlong), ("plan_index", _c_int), ("t_arrival", _c_double),
+                ("t_admit", _c_double), ("t_done", _c_double), ("status", _c_int)]
+
+
+lib.spp_server_create.argtypes = [_c_int, _vpp, _vp, _c_size_t, _c_int, ctypes.POINTER(_vp)]
+lib.spp_server_create.restype = _c_int
+lib.spp_server_submit.argtypes = [_vp, ctypes.POINTER(_Request), _c_double]
+lib.spp_server_submit.restype = _c_int
+lib.spp_server_poll.argtypes = [_vp, ctypes.POINTER(_Completion), _c_int, ctypes.POINTER(_c_int)]
+lib.spp_server_poll.restype = _c_int
+lib.spp_server_drain.argtypes = [_vp, _c_double]
+lib.spp_server_drain.restype = _c_int
+lib.spp_server_now.argtypes = [_vp, ctypes.POINTER(_c_double)]
+lib.spp_server_now.restype = _c_int
+lib.spp_server_destroy.argtypes = [_vp]
+lib.spp_server_destroy.restype = None
 lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
 lib.spp_theta_eigensystem.restype = _c_int
 lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
@@ -239,3 +263,57 @@ class Batch:
         if b is not None and b.value:
             lib.spp_batch_destroy(b)
             self._batch = None
+
+
+class Server:
+    """Serving loop with continuous batching (see spp_server_create).
+
+    ``Server(plans, pool_bytes, n_slots)`` allocates the workspace pool as a
+    torch uint8 tensor on the plans' device.  ``submit`` queues a request
+    (tensors are kept alive until its completion is polled); ``poll`` returns
+    completion records as dicts; ``drain`` waits for all submitted requests.
+    """
+
+    def __init__(self, plans, pool_bytes, n_slots=8):
+        import torch
+        self.plans = list(plans)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.plans[0].device)
+        arr = (_vp * len(self.plans))(*[p._plan for p in self.plans])
+        s = _vp()
+        _check(lib.spp_server_create(len(self.plans), arr, _vp(self.pool.data_ptr()), self.pool.numel(),
+                                     int(n_slots), ctypes.byref(s)), "spp_server_create")
+        self._s = s
+        self._live = {}
+
+    def now(self):
+        t = _c_double()
+        _check(lib.spp_server_now(self._s, ctypes.byref(t)), "spp_server_now")
+        return t.value
+
+    def submit(self, plan_index, rho, phi, G=1.0, request_id=0, not_before=0.0):
+        req = _Request(int(plan_index), _vp(rho.data_ptr()), _vp(phi.data_ptr()), float(G), int(request_id))
+        _check(lib.spp_server_submit(self._s, ctypes.byref(req), float(not_before)), "spp_server_submit")
+        self._live[int(request_id)] = (rho, phi)
+
+    def poll(self, max_out=4096):
+        buf = (_Completion * max_out)()
+        n = _c_int()
+        _check(lib.spp_server_poll(self._s, buf, max_out, ctypes.byref(n)), "spp_server_poll")
+        out = []
+        for c in buf[:n.value]:
+            self._live.pop(int(c.request_id), None)
+            out.append(dict(request_id=c.request_id, plan_index=c.plan_index, t_arrival=c.t_arrival,
+                            t_admit=c.t_admit, t_done=c.t_done, status=c.status))
+        return out
+
+    def drain(self, timeout_s=120.0):
+        _check(lib.spp_server_drain(self._s, float(timeout_s)), "spp_server_drain")
+
+    def close(self):
+        s = getattr(self, "_s", None)
+        if s is not None and s.value:
+            lib.spp_server_destroy(s)
+            self._s = None
+
+    def __del__(self):
+        self.close()
