@@ -34,13 +34,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_model(nr, nth, nphi):
-    """Algorithmic bytes and flops per launch of each stage (FP64)."""
+def stage_model(nr, nth, nphi, parity):
+    """Algorithmic bytes and flops per launch of each stage (FP64).
+
+    With the parity split each N_theta^2 product per Fourier component becomes
+    two (N_theta/2)^2 products: half the flops and half the matrix bytes.
+    """
     n = nr * nth * nphi
     field = 8.0 * n                                   # one real field, bytes
     nm = nphi // 2 + 1
-    basis = 8.0 * nm * nth * nth                      # one set of per-m matrices
-    proj_flops = 2.0 * nr * nth * nth * nphi          # N_phi real components, K = N_theta
+    basis = 8.0 * nm * nth * nth * (0.5 if parity else 1.0)
+    proj_flops = 2.0 * nr * nth * nth * nphi * (0.5 if parity else 1.0)
     return {
         "fft_forward": {"bytes": 2 * field, "flops": None},
         "projection_forward": {"bytes": 2 * field + basis, "flops": proj_flops},
@@ -250,7 +254,7 @@ def main():
     # per-stage durations (HIP events recorded by the library on the solve stream)
     st = np.array([plan.solve_profiled(rho, phi, G=case["G"]) for _ in range(args.profile_steps)])
     stage_ms = st.mean(axis=0)
-    model = stage_model(nr, nth, nphi)
+    model = stage_model(nr, nth, nphi, plan.parity_split)
     stages = {}
     for name, ms in zip(STAGES, stage_ms):
         m = model[name]
@@ -267,11 +271,13 @@ def main():
     proj_ms = 0.5 * (stage_ms[1] + stage_ms[3])
     proj_flops = model["projection_forward"]["flops"]
     achieved = proj_flops / (proj_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "k_proj_f64", "achieved": round(achieved, 3),
+    kname = "proj::k_proj_par (parity split)" if plan.parity_split else "proj::k_proj_f64"
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
                 "traffic": None,
-                "per_launch": f"2*N_r*N_theta^2*N_phi = {proj_flops:.4g} flop per launch "
-                              f"(all N_phi real Fourier components), avg launch {proj_ms * 1e3:.1f} us"}
+                "per_launch": (f"{'N_r*N_theta^2*N_phi (parity split)' if plan.parity_split else '2*N_r*N_theta^2*N_phi'}"
+                               f" = {proj_flops:.4g} flop per launch "
+                               f"(all N_phi real Fourier components), avg launch {proj_ms * 1e3:.1f} us")}
 
     # mixed-precision form on the same workload (FP32-MFMA projections + FP64 refinement)
     mixed = None

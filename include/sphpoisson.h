@@ -254,10 +254,20 @@ void spp_server_destroy(spp_server s);
 /*
  * Host copy of the theta eigensystem of mode m (0 <= m <= N_phi/2), for tests:
  *   H    host, N_theta*N_theta doubles, H[j*N_theta + l] = H_{l,m}(j);
- *   lam  host, N_theta doubles, lambda_{Omega,l,m} in ascending order.
+ *   lam  host, N_theta doubles, lambda_{Omega,l,m}: in ascending order, or,
+ *        on theta grids symmetric about the equator (even N_theta), the
+ *        N_theta/2 even modes in ascending order followed by the odd ones.
  * Errors: SPP_EINVAL.
  */
 spp_status spp_theta_eigensystem(spp_plan p, int m, double* H, double* lam);
+
+/*
+ * *on = 1 if the FP64 solves of this plan use the parity-split projection
+ * (Sec. 4.2: theta grid symmetric about the equator, even N_theta <= 128;
+ * two (N_theta/2)^2 products per Fourier component instead of one
+ * N_theta^2 product), else 0.  Errors: SPP_EINVAL.
+ */
+spp_status spp_plan_parity_split(spp_plan p, int* on);
 
 /* Grid sizes of a plan (any pointer may be NULL). */
 spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi);

@@ -78,6 +78,8 @@ lib.spp_server_now.argtypes = [_vp, ctypes.POINTER(_c_double)]
 lib.spp_server_now.restype = _c_int
 lib.spp_server_destroy.argtypes = [_vp]
 lib.spp_server_destroy.restype = None
+lib.spp_plan_parity_split.argtypes = [_vp, ctypes.POINTER(_c_int)]
+lib.spp_plan_parity_split.restype = _c_int
 lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
 lib.spp_theta_eigensystem.restype = _c_int
 lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
@@ -146,6 +148,12 @@ class Plan:
             self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
             _check(lib.spp_plan_upload(plan, _vp(self._plan_dev.data_ptr()), _stream_ptr(None)),
                    "spp_plan_upload")
+
+    @property
+    def parity_split(self):
+        on = _c_int()
+        _check(lib.spp_plan_parity_split(self._plan, ctypes.byref(on)), "spp_plan_parity_split")
+        return bool(on.value)
 
     @property
     def shape(self):

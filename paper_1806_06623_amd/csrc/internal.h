@@ -28,6 +28,8 @@ struct spp_plan_layout {
     size_t Himg = 0;    // LDS images of H_m, [M][KMAX][NP]
     size_t Wimg32 = 0;  // FP32 copies of the images (mixed-precision projections)
     size_t Himg32 = 0;
+    size_t Wpar = 0;    // parity-split images, [M][2][KMAX][NP] (even, odd)
+    size_t Hpar = 0;
     size_t sig = 0;     // theta face coefficients sigma_{j+1/2}, [N_theta + 1] (poles 0)
     size_t dmu = 0;     // cos theta_{j-1/2} - cos theta_{j+1/2}, [N_theta]
     size_t Sj = 0;      // S_j, [N_theta]
@@ -41,7 +43,10 @@ struct spp_plan_s {
     // host tables (float64), layouts as in spp_plan_layout
     std::vector<double> tw, W, H, lam, beta, alpha, V, VR, Wimg, Himg, sig, dmu, Sj, lamphi;
     std::vector<float> Wimg32, Himg32;
+    std::vector<double> Ue, Uo, Wpar, Hpar;   // half-size even/odd eigenvectors and their images
     int proj_rn = 0;                           // tile width of the projection kernel (0: fallback)
+    bool parity = false;                       // equator-symmetric theta grid: modes ordered even, odd
+    int par_rn = 0;                            // tile width of the parity-split kernel (0: not used)
     spp_plan_layout lay;
     size_t workspace_bytes = 0;
     void* dev = nullptr;                       // caller-owned device copy

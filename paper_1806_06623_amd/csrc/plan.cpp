@@ -146,33 +146,77 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         std::vector<double> isd(nth);
         for (int j = 0; j < nth; ++j) isd[j] = 1.0 / std::sqrt(G.dmu[j]);
 
+        // Equator-symmetric theta grids (Sec. 4.2, parity split): the theta
+        // operator commutes with j -> N_theta-1-j, so its eigenvectors are even
+        // or odd.  They are computed from the half-size even and odd operators
+        // directly (near-degenerate pairs of the full operator may otherwise
+        // mix parities): on j < h = N_theta/2 the reflected neighbour of the
+        // last cell is the cell itself (+sigma_h for even, -sigma_h for odd).
+        // Modes are then ordered even first, then odd.
+        bool symmetric = nth % 2 == 0 && nth >= 4;
+        for (int j = 0; symmetric && j <= nth; ++j)
+            symmetric = std::fabs(g->th_if[j] + g->th_if[nth - j] - M_PI) <= 1e-12 * M_PI;
+        const int hh = nth / 2;
+        p->parity = symmetric;
+        if (symmetric) {
+            p->Ue.assign(size_t(nm) * hh * hh, 0.0);
+            p->Uo.assign(size_t(nm) * hh * hh, 0.0);
+        }
+
         bool ok = true;
+        auto set_lam = [&](int m, int l, double lam) {
+            p->lam[size_t(m) * nth + l] = lam;
+            // outer face: flux / (dmu dphi) = -beta f_N with
+            // beta = p r_o (r_o / r_N)^-p, p = (1 + sqrt(1 - 4 lambda))/2
+            const double pp = 0.5 * (1.0 + std::sqrt(std::max(0.0, 1.0 - 4.0 * lam)));
+            p->beta[size_t(m) * nth + l] = pp * ro * std::exp(-pp * log_ratio);
+        };
         auto work = [&](int m0, int stride) {
             std::vector<double> d(nth), e(nth > 1 ? nth - 1 : 0), Z;
             for (int m = m0; m < nm; m += stride) {
                 const double sm = std::sin(0.5 * m * dphi) / (0.5 * dphi);
                 const double lam_phi = -sm * sm;   // eigenvalue of the phi second difference
+                double* Hm = &p->H[size_t(m) * nth * nth];
+                double* Wm = &p->W[size_t(m) * nth * nth];
+                if (symmetric) {
+                    const double r2 = std::sqrt(0.5);
+                    for (int par = 0; par < 2; ++par) {
+                        std::vector<double> dh(hh), eh(hh - 1), Zh;
+                        for (int j = 0; j < hh; ++j) {
+                            double k = -(G.sigma[j] + G.sigma[j + 1]) + G.dth[j] * lam_phi / std::sin(G.th[j]);
+                            if (j == hh - 1) k += par == 0 ? G.sigma[hh] : -G.sigma[hh];
+                            dh[j] = k * isd[j] * isd[j];
+                        }
+                        for (int j = 0; j + 1 < hh; ++j) eh[j] = G.sigma[j + 1] * isd[j] * isd[j + 1];
+                        if (!spp_tridiag_eigen(hh, dh, eh, Zh)) { ok = false; return; }
+                        double* U = &(par == 0 ? p->Ue : p->Uo)[size_t(m) * hh * hh];
+                        const double sgn = par == 0 ? 1.0 : -1.0;
+                        for (int j = 0; j < hh; ++j)
+                            for (int l = 0; l < hh; ++l) {
+                                const double u = Zh[size_t(j) * hh + l] * isd[j];   // D_h-orthonormal half vector
+                                U[size_t(j) * hh + l] = u;
+                                const int col = par * hh + l;
+                                Hm[size_t(j) * nth + col] = u * r2;
+                                Hm[size_t(nth - 1 - j) * nth + col] = sgn * u * r2;
+                            }
+                        for (int l = 0; l < hh; ++l) set_lam(m, par * hh + l, dh[l]);
+                    }
+                    for (int j = 0; j < nth; ++j)
+                        for (int l = 0; l < nth; ++l) Wm[size_t(l) * nth + j] = Hm[size_t(j) * nth + l] * G.dmu[j];
+                    continue;
+                }
                 for (int j = 0; j < nth; ++j)
                     d[j] = (-(G.sigma[j] + G.sigma[j + 1]) + G.dth[j] * lam_phi / std::sin(G.th[j]))
                            * isd[j] * isd[j];
                 for (int j = 0; j + 1 < nth; ++j) e[j] = G.sigma[j + 1] * isd[j] * isd[j + 1];
                 if (!spp_tridiag_eigen(nth, d, e, Z)) { ok = false; return; }
-                double* Hm = &p->H[size_t(m) * nth * nth];
-                double* Wm = &p->W[size_t(m) * nth * nth];
                 for (int j = 0; j < nth; ++j)
                     for (int l = 0; l < nth; ++l) {
                         const double h = Z[size_t(j) * nth + l] * isd[j];   // H = D^-1/2 V
                         Hm[size_t(j) * nth + l] = h;
                         Wm[size_t(l) * nth + j] = h * G.dmu[j];            // H^-1 = H^T D
                     }
-                for (int l = 0; l < nth; ++l) {
-                    const double lam = d[l];
-                    p->lam[size_t(m) * nth + l] = lam;
-                    // outer face: flux / (dmu dphi) = -beta f_N with
-                    // beta = p r_o (r_o / r_N)^-p, p = (1 + sqrt(1 - 4 lambda))/2
-                    const double pp = 0.5 * (1.0 + std::sqrt(std::max(0.0, 1.0 - 4.0 * lam)));
-                    p->beta[size_t(m) * nth + l] = pp * ro * std::exp(-pp * log_ratio);
-                }
+                for (int l = 0; l < nth; ++l) set_lam(m, l, d[l]);
             }
         };
         const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
@@ -215,6 +259,31 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             p->Himg32.assign(p->Himg.begin(), p->Himg.end());
         }
 
+        // LDS images of the half-size even/odd matrices for the parity-split
+        // projection kernel ([m][parity][KMAX][NP], K = h <= 64):
+        //   forward  B_p[l][j] = U_p[j][l] dmu_j / sqrt 2   (applied to s_j +- s_{N-1-j})
+        //   inverse  B_p[j][l] = U_p[j][l] / sqrt 2         (g_j, g_{N-1-j} = G_e +- G_o)
+        if (symmetric && hh <= 64) {
+            const int rn = projimg::rn_for(hh);
+            const size_t ie = projimg::elems(rn);
+            const int NP = projimg::np(rn), KG = projimg::kpad(hh) / 4;
+            const double r2 = std::sqrt(0.5);
+            p->par_rn = rn;
+            p->Wpar.assign(size_t(nm) * 2 * ie, 0.0);
+            p->Hpar.assign(size_t(nm) * 2 * ie, 0.0);
+            for (int m = 0; m < nm; ++m)
+                for (int par = 0; par < 2; ++par) {
+                    const double* U = &(par == 0 ? p->Ue : p->Uo)[size_t(m) * hh * hh];
+                    const size_t base = (size_t(m) * 2 + par) * ie;
+                    for (int n = 0; n < hh; ++n)
+                        for (int k = 0; k < hh; ++k) {
+                            const size_t dst = base + size_t(projimg::row_of(k, KG)) * NP + n;
+                            p->Wpar[dst] = U[size_t(k) * hh + n] * G.dmu[k] * r2;   // n = l, k = j
+                            p->Hpar[dst] = U[size_t(n) * hh + k] * r2;              // n = j, k = l
+                        }
+                }
+        }
+
         // device layout
         spp_plan_layout& L = p->lay;
         size_t off = 0;
@@ -240,6 +309,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.Himg = take(p->Himg.size());
         L.Wimg32 = take_f(p->Wimg32.size());
         L.Himg32 = take_f(p->Himg32.size());
+        L.Wpar = take(p->Wpar.size());
+        L.Hpar = take(p->Hpar.size());
         L.sig = take(p->sig.size());
         L.dmu = take(p->dmu.size());
         L.Sj = take(p->Sj.size());
@@ -274,6 +345,13 @@ extern "C" spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi)
     return SPP_OK;
 }
 
+extern "C" spp_status spp_plan_parity_split(spp_plan p, int* on)
+{
+    if (!p || !on) return spp_fail(SPP_EINVAL, "spp_plan_parity_split: NULL pointer");
+    *on = p->par_rn != 0 ? 1 : 0;
+    return SPP_OK;
+}
+
 extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
 {
     if (!p || !plan_dev) return spp_fail(SPP_EINVAL, "spp_plan_upload: NULL pointer");
@@ -295,6 +373,8 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.Himg, p->Himg);
     std::memcpy(img.data() + p->lay.Wimg32, p->Wimg32.data(), p->Wimg32.size() * sizeof(float));
     std::memcpy(img.data() + p->lay.Himg32, p->Himg32.data(), p->Himg32.size() * sizeof(float));
+    put(p->lay.Wpar, p->Wpar);
+    put(p->lay.Hpar, p->Hpar);
     put(p->lay.sig, p->sig);
     put(p->lay.dmu, p->dmu);
     put(p->lay.Sj, p->Sj);

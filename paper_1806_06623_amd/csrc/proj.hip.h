@@ -168,6 +168,162 @@ __global__ __launch_bounds__(64 * NW) void k_proj_f64(const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Parity-split projection (Sec. 4.2) for theta grids symmetric about the
+// equator, N = N_theta = 2h: the eigenvectors are even or odd in j, so each
+// N x N product becomes two h x h products on the folded data.
+//   forward (FWD): A_e[k] = s_k + s_{N-1-k}, A_o[k] = s_k - s_{N-1-k} (k < h);
+//                  C[l] = (B_e A_e)[l] for l < h, C[h + l] = (B_o A_o)[l]
+//                  (modes ordered even, then odd);
+//   inverse:       A_e = f[0..h), A_o = f[h..N);
+//                  C[j] = G_e[j] + G_o[j], C[N-1-j] = G_e[j] - G_o[j], G_p = B_p A_p.
+// B_e and B_o (images of K = h) are staged together in LDS.
+template <int RM, bool KVEC, bool FWD>
+__device__ __forceinline__ void load_chunk_par(double (&x)[RM][8], double (&z)[RM][8], const double* __restrict__ Aq,
+                                               int M, int N, int h, int rbase, int lr, int k0)
+{
+#pragma unroll
+    for (int rb = 0; rb < RM; ++rb) {
+        const int row = rbase + rb * 16 + lr;
+        const double* src = Aq + size_t(row < M ? row : M - 1) * N;
+        // second operand: mirrored run N-8-k0 .. N-1-k0 (forward) or h+k0 .. (inverse)
+        const int z0 = FWD ? N - 8 - k0 : h + k0;
+        if constexpr (KVEC) {
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                const double2 a = *reinterpret_cast<const double2*>(src + k0 + u);
+                const double2 b = *reinterpret_cast<const double2*>(src + z0 + u);
+                x[rb][u] = a.x;
+                x[rb][u + 1] = a.y;
+                z[rb][u] = b.x;
+                z[rb][u + 1] = b.y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u < h ? k0 + u : h - 1;   // k >= h meets zero rows of B
+                x[rb][u] = src[k];
+                const int kz = FWD ? N - 8 - k0 + u : h + k0 + u;
+                z[rb][u] = src[kz < 0 ? 0 : (kz < N ? kz : N - 1)];
+            }
+        }
+    }
+}
+
+template <int RN, int RM, bool FWD>
+__device__ __forceinline__ void mfma_chunk_par(d4 (&ae)[RM][RN], d4 (&ao)[RM][RN], const double (&x)[RM][8],
+                                               const double (&z)[RM][8], const double* __restrict__ Be,
+                                               const double* __restrict__ Bo, int NP, int s0, int g, int lr)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double* re = Be + (4 * (s0 + u) + g) * NP + lr;
+        const double* ro = Bo + (4 * (s0 + u) + g) * NP + lr;
+        double be[RN], bo[RN];
+#pragma unroll
+        for (int cb = 0; cb < RN; ++cb) {
+            be[cb] = re[cb * 16];
+            bo[cb] = ro[cb * 16];
+        }
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb) {
+            const double ev = FWD ? x[rb][u] + z[rb][7 - u] : x[rb][u];
+            const double od = FWD ? x[rb][u] - z[rb][7 - u] : z[rb][u];
+#pragma unroll
+            for (int cb = 0; cb < RN; ++cb) {
+                ae[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ev, be[cb], ae[rb][cb], 0, 0, 0);
+                ao[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(od, bo[cb], ao[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int RN, int RM, bool KVEC, bool FWD, int NW = NWAVES>
+__global__ __launch_bounds__(64 * NW) void k_proj_par(const double* __restrict__ A, const double* __restrict__ Bpar,
+                                                      double* __restrict__ C, int M, int N, int nphi, int splits)
+{
+    using S = Shape<RN>;
+    __shared__ double Bs[2 * S::ELEMS];
+
+    const int q = blockIdx.y;
+    const int m = q <= nphi / 2 ? q : nphi - q;
+    const int h = N / 2;
+    const double* __restrict__ Aq = A + size_t(q) * M * N;
+    double* __restrict__ Cq = C + size_t(q) * M * N;
+    const int KG = ((h + 31) & ~31) >> 2;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, g = lane >> 4;
+    const int kb0 = g * KG;
+    double xa[RM][8], za[RM][8], xb[RM][8], zb[RM][8];
+    {
+        const int gi0 = blockIdx.x * NW + wave;
+        load_chunk_par<RM, KVEC, FWD>(xa, za, Aq, M, N, h, gi0 * 16 * RM < M ? gi0 * 16 * RM : 0, lr, kb0);
+    }
+    {
+        const double2* src = reinterpret_cast<const double2*>(Bpar + size_t(m) * 2 * S::ELEMS);
+        double2* dst = reinterpret_cast<double2*>(Bs);
+        constexpr int TH = 64 * NW, HALF = S::ELEMS, PER = (HALF + TH - 1) / TH;   // 2*ELEMS doubles
+        double2 v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TH;
+            v[u] = src[i < HALF ? i : HALF - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TH;
+            if (i < HALF) dst[i] = v[u];
+        }
+    }
+    __syncthreads();
+    const double* Be = Bs;
+    const double* Bo = Bs + S::ELEMS;
+
+    const int ngroups = (M + 16 * RM - 1) / (16 * RM);
+    for (int gi = blockIdx.x * NW + wave; gi < ngroups; gi += NW * splits) {
+        const int rbase = gi * 16 * RM;
+        d4 ae[RM][RN], ao[RM][RN];
+#pragma unroll
+        for (int a = 0; a < RM; ++a)
+#pragma unroll
+            for (int b = 0; b < RN; ++b) {
+                ae[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                ao[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            }
+        if (gi != blockIdx.x * NW + wave) load_chunk_par<RM, KVEC, FWD>(xa, za, Aq, M, N, h, rbase, lr, kb0);
+        for (int s0 = 0; s0 < KG; s0 += 16) {
+            const int s1 = s0 + 8 < KG ? s0 + 8 : KG - 8;
+            load_chunk_par<RM, KVEC, FWD>(xb, zb, Aq, M, N, h, rbase, lr, kb0 + s1);
+            mfma_chunk_par<RN, RM, FWD>(ae, ao, xa, za, Be, Bo, S::NP, s0, g, lr);
+            const int s2 = s0 + 16 < KG ? s0 + 16 : KG - 8;
+            load_chunk_par<RM, KVEC, FWD>(xa, za, Aq, M, N, h, rbase, lr, kb0 + s2);
+            if (s0 + 8 < KG) mfma_chunk_par<RN, RM, FWD>(ae, ao, xb, zb, Be, Bo, S::NP, s0 + 8, g, lr);
+        }
+
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < RN; ++cb) {
+                const int col = cb * 16 + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rbase + rb * 16 + g + 4 * v;
+                    if (row < M && col < h) {
+                        double* c = Cq + size_t(row) * N;
+                        if (FWD) {
+                            c[col] = ae[rb][cb][v];
+                            c[h + col] = ao[rb][cb][v];
+                        } else {
+                            c[col] = ae[rb][cb][v] + ao[rb][cb][v];
+                            c[N - 1 - col] = ae[rb][cb][v] - ao[rb][cb][v];
+                        }
+                    }
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP32 variant for the mixed-precision solve: the same tiling, with A rounded
 // to float in registers, B_m taken from an FP32 image of the same layout, and
 // v_mfma_f32_16x16x4f32 products accumulated in FP32.  Its result register v

@@ -316,7 +316,6 @@ int device_cus()
     return cus;
 }
 
-// Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
 // Rows per wave tile (16 RM) of the projection kernel.  The default depends on
 // the tile width; spp_autotune_projection may record a measured choice per
 // (N_theta, N_r), which then takes precedence.
@@ -373,6 +372,36 @@ bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, i
         if (rm == 2) SPP_PROJ(1, 2); else SPP_PROJ(1, 4);
     }
 #undef SPP_PROJ
+    return true;
+}
+
+// Parity-split projection for equator-symmetric theta grids (h = N_theta/2 <= 64).
+bool launch_proj_par(const double* A, const double* Bpar, double* C, int M, int N, int nphi, bool fwd, int rn,
+                     hipStream_t s)
+{
+    if (rn == 0) return false;
+    const int h = N / 2;
+    const int rm = 1;
+    const int groups = (M + 16 * rm - 1) / (16 * rm);
+    int splits = (device_cus() + nphi - 1) / nphi;
+    const int maxsplits = (groups + proj::NWAVES - 1) / proj::NWAVES;
+    if (splits > maxsplits) splits = maxsplits;
+    if (splits < 1) splits = 1;
+    const dim3 grid(splits, nphi), block(64 * proj::NWAVES);
+    const bool kvec = (h % 32) == 0;
+#define SPP_PAR(RN, KV)                                                                                        \
+    do {                                                                                                       \
+        if (fwd)                                                                                               \
+            hipLaunchKernelGGL((proj::k_proj_par<RN, 1, KV, true>), grid, block, 0, s, A, Bpar, C, M, N, nphi, splits);  \
+        else                                                                                                   \
+            hipLaunchKernelGGL((proj::k_proj_par<RN, 1, KV, false>), grid, block, 0, s, A, Bpar, C, M, N, nphi, splits); \
+    } while (0)
+    switch (rn) {
+    case 1: if (kvec) SPP_PAR(1, true); else SPP_PAR(1, false); break;
+    case 2: if (kvec) SPP_PAR(2, true); else SPP_PAR(2, false); break;
+    default: if (kvec) SPP_PAR(4, true); else SPP_PAR(4, false); break;
+    }
+#undef SPP_PAR
     return true;
 }
 
@@ -586,6 +615,8 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
     const double* VR = reinterpret_cast<const double*>(base + p->lay.VR);
     const double* Wimg = reinterpret_cast<const double*>(base + p->lay.Wimg);
     const double* Himg = reinterpret_cast<const double*>(base + p->lay.Himg);
+    const double* Wpar = reinterpret_cast<const double*>(base + p->lay.Wpar);
+    const double* Hpar = reinterpret_cast<const double*>(base + p->lay.Hpar);
 
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
     const int nlines = nr * nth;
@@ -603,7 +634,7 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
     mark(1);
     const dim3 pgrid((nth + PBN - 1) / PBN, (nr + PBM - 1) / PBM, nphi);
-    if (!launch_proj(X, Wimg, Y, nr, nth, nphi, s))
+    if (!launch_proj_par(X, Wpar, Y, nr, nth, nphi, true, p->par_rn, s) && !launch_proj(X, Wimg, Y, nr, nth, nphi, s))
         hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
     mark(2);
     const int nsys = nphi * nth;
@@ -611,7 +642,7 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR,
                            nr, nth, nphi);
     mark(3);
-    if (!launch_proj(Y, Himg, X, nr, nth, nphi, s))
+    if (!launch_proj_par(Y, Hpar, X, nr, nth, nphi, false, p->par_rn, s) && !launch_proj(Y, Himg, X, nr, nth, nphi, s))
         hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
     mark(4);
     launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s);
