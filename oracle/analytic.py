@@ -3,6 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 """
 import numpy as np
+from scipy.special import elliprd, elliprf
 
 
 def uniform_sphere_potential(r, R, rho0=1.0, G=1.0):
@@ -39,3 +40,35 @@ def spherical_discrete_potential(r_if, s_radial):
     for i in range(r.size - 2, -1, -1):
         f[i] = f[i + 1] - Q[i] * (r[i + 1] - r[i]) / r_if[i + 1] ** 2
     return f
+
+
+def ellipsoid_potential(x, y, z, a, b, c, rho0=1.0, G=1.0):
+    """Potential of a homogeneous ellipsoid with semi-axes a, b, c along x, y, z
+    (the closed form quoted in Sec. 5.2, Chandrasekhar 1969):
+
+        Phi = pi G rho0 a b c (A x^2 + B y^2 + C z^2 - D),
+
+    A, B, C, D the integrals over lambda from u to infinity of
+    [(a^2+l)^3 (b^2+l)(c^2+l)]^-1/2, ... and [(a^2+l)(b^2+l)(c^2+l)]^-1/2, with u = 0
+    inside and u the root of x^2/(a^2+u) + y^2/(b^2+u) + z^2/(c^2+u) = 1 outside.
+    The integrals are Carlson's symmetric forms: D = 2 R_F(a^2+u, b^2+u, c^2+u),
+    A = (2/3) R_D(b^2+u, c^2+u, a^2+u) and cyclically for B, C.
+    """
+    x, y, z = (np.asarray(v, dtype=np.float64) for v in (x, y, z))
+    a2, b2, c2 = a * a, b * b, c * c
+    u = np.zeros(np.broadcast(x, y, z).shape)
+    x, y, z = np.broadcast_arrays(x, y, z)
+    out = x * x / a2 + y * y / b2 + z * z / c2 > 1.0
+    xo, yo, zo = x[out], y[out], z[out]
+    # the left side decreases monotonically in u; Newton from u = r^2 - a^2
+    uo = np.maximum(xo * xo + yo * yo + zo * zo - a2, 0.0)
+    for _ in range(60):
+        f = xo * xo / (a2 + uo) + yo * yo / (b2 + uo) + zo * zo / (c2 + uo) - 1.0
+        df = -(xo * xo / (a2 + uo) ** 2 + yo * yo / (b2 + uo) ** 2 + zo * zo / (c2 + uo) ** 2)
+        uo = np.maximum(uo - f / df, 0.0)
+    u[out] = uo
+    A = 2.0 / 3.0 * elliprd(b2 + u, c2 + u, a2 + u)
+    B = 2.0 / 3.0 * elliprd(a2 + u, c2 + u, b2 + u)
+    C = 2.0 / 3.0 * elliprd(a2 + u, b2 + u, c2 + u)
+    D = 2.0 * elliprf(a2 + u, b2 + u, c2 + u)
+    return np.pi * G * rho0 * a * b * c * (A * x * x + B * y * y + C * z * z - D)
