@@ -54,6 +54,31 @@ def stage_model(nr, nth, nphi, parity):
     }
 
 
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (profiles/proj_par_550x128x256_hbm_traffic.md), scaled by the same
+# counters read over a device copy of known size.  Valid only for the kernel
+# sources it was taken with: if they have changed, the figure is withheld.
+TRAFFIC = {"kernel": "proj::k_proj_par", "grid": (550, 128, 256), "source_digest": "91582cb9df19b01c",
+           "bytes_per_launch": 0.5 * ((116247.5 + 126847.7) * 2.0 + 2 * 140800.0) * 1024.0}
+
+
+def _kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("proj.hip.h", "solve.hip", "proj_layout.h"):
+        with open(os.path.join(ROOT, "paper_1806_06623_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(parity, nr, nth, nphi):
+    t = TRAFFIC
+    if (t is None or not parity or (nr, nth, nphi) != tuple(t["grid"])
+            or _kernel_source_digest() != t["source_digest"]):
+        return None
+    return round(t["bytes_per_launch"], 0)
+
+
 def cpu_baseline(case, phi_gpu, seconds):
     """The FP64 oracle, as it stands, on the host cores (set-up excluded)."""
     from oracle import spectral
@@ -267,17 +292,28 @@ def main():
         stages[name] = d
     log("stages: " + ", ".join(f"{k}={v['ms']:.4f}ms" for k, v in stages.items()))
 
-    # dominant kernel: the theta projection GEMM (two launches per solve)
+    # dominant kernel: the theta projection (two launches per solve).  Its
+    # roofline is the larger of the two ideal times: algorithmic bytes at the
+    # HBM peak, algorithmic flops at the FP64 matrix peak.  With the parity
+    # split the flops halve and the bytes bound it.
     proj_ms = 0.5 * (stage_ms[1] + stage_ms[3])
-    proj_flops = model["projection_forward"]["flops"]
-    achieved = proj_flops / (proj_ms * 1e-3) / 1e12
+    pm = model["projection_forward"]
+    t_hbm = pm["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_mfma = pm["flops"] / (FP64_PEAK_TFLOPS * 1e12)
     kname = "proj::k_proj_par (parity split)" if plan.parity_split else "proj::k_proj_f64"
-    roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None,
-                "per_launch": (f"{'N_r*N_theta^2*N_phi (parity split)' if plan.parity_split else '2*N_r*N_theta^2*N_phi'}"
-                               f" = {proj_flops:.4g} flop per launch "
-                               f"(all N_phi real Fourier components), avg launch {proj_ms * 1e3:.1f} us")}
+    if t_hbm >= t_mfma:
+        achieved, peak, unit = pm["bytes"] / (proj_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = pm["flops"] / (proj_ms * 1e-3) / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+    roofline = {"bound": "hbm" if t_hbm >= t_mfma else "mfma", "kernel": kname,
+                "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(plan.parity_split, nr, nth, nphi),
+                "per_launch": (f"{pm['bytes']:.4g} algorithmic bytes (rho-spectrum in, projected spectrum out, "
+                               f"one basis per m) and {pm['flops']:.4g} flop "
+                               f"({'N_r*N_theta^2*N_phi, parity split' if plan.parity_split else '2*N_r*N_theta^2*N_phi'}) "
+                               f"per launch; avg launch {proj_ms * 1e3:.1f} us (HIP events on the solve stream); "
+                               f"ideal {t_hbm * 1e6:.1f} us at the HBM peak, {t_mfma * 1e6:.1f} us at the FP64 "
+                               f"matrix peak")}
 
     # mixed-precision form on the same workload (FP32-MFMA projections + FP64 refinement)
     mixed = None
