@@ -61,13 +61,32 @@ def theta_eigensystem(geom, m):
     Solves K H = lambda D H through the symmetric tridiagonal matrix
     D^-1/2 K D^-1/2 (scipy's eigh_tridiagonal with LAPACK's implicit QL/QR
     driver 'stev', whose eigenvectors are orthonormal to rounding), then
-    H = D^-1/2 V, which makes H^T D H = I.
+    H = D^-1/2 V, which makes H^T D H = I.  For m = 0 the null pair is exact
+    (see below).
     """
     lam_phi = phi_eigenvalues(geom["nphi"])[m]
     diag, off = theta_operator(geom, lam_phi)
-    w = 1.0 / np.sqrt(geom["dmu"])
+    dmu = geom["dmu"]
+    w = 1.0 / np.sqrt(dmu)
     lam, vec = eigh_tridiagonal(diag * w * w, off * w[:-1] * w[1:], lapack_driver="stev")
-    return lam, w[:, None] * vec
+    H = w[:, None] * vec
+    if m == 0:
+        # No flux crosses the poles (Sec. 3.1), so for m = 0 every row of K
+        # sums to zero: the constant is an exact eigenvector with eigenvalue
+        # 0, the largest (K is negative semidefinite).  It is used exactly;
+        # a computed one is off by about eps |K| / gap, which the large radial
+        # response of this mode would carry into Phi.  The other eigenvectors
+        # are made exactly D-orthogonal to it.
+        i = int(np.argmax(lam))
+        c = np.full(dmu.size, 1.0 / np.sqrt(np.sum(dmu)))
+        rest = np.arange(dmu.size) != i
+        Hr = H[:, rest]
+        Hr = Hr - np.outer(c, c @ (dmu[:, None] * Hr))
+        H[:, rest] = Hr / np.sqrt(np.sum(dmu[:, None] * Hr * Hr, axis=0))
+        H[:, i] = c
+        lam = lam.copy()
+        lam[i] = 0.0
+    return lam, H
 
 
 def outer_beta(geom, lam):

@@ -157,14 +157,16 @@ def test_reciprocity_of_spectral_solutions():
     assert abs(pa[b] - pb[a]) < 1e-13 * abs(pa[b])
 
 
-def test_spherical_source_closed_form():
-    """A spherically symmetric source excites only l = m = 0: discrete Gauss's law."""
-    r_if = synthetic.stellar_r_interfaces(128)
-    th_if = synthetic.theta_interfaces(16)
-    nphi = 16
+@pytest.mark.parametrize("nr,nth,nphi", [(128, 16, 16), (385, 128, 8)])
+def test_spherical_source_closed_form(nr, nth, nphi):
+    """A spherically symmetric source excites only l = m = 0: discrete Gauss's
+    law.  At N_theta = 128 a computed (not exact) m = 0 null eigenvector is off
+    by about 1e-12 and fails this bar."""
+    r_if = synthetic.stellar_r_interfaces(nr)
+    th_if = synthetic.theta_interfaces(nth)
     r = 0.5 * (r_if[:-1] + r_if[1:])
     rho_r = (1 + (r / 20.0) ** 2) ** -1.5
-    rho = np.broadcast_to(rho_r[:, None, None], (128, 16, nphi)).copy()
+    rho = np.broadcast_to(rho_r[:, None, None], (nr, nth, nphi)).copy()
     phi = spectral.solve(r_if, th_if, nphi, rho)
     f = analytic.spherical_discrete_potential(r_if, 4 * np.pi * rho_r)
     assert rel(phi, np.broadcast_to(f[:, None, None], phi.shape)) < 1e-13
