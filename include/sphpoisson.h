@@ -56,6 +56,12 @@ typedef enum {
     SPP_MIXED_BF16X3 = 2   /* split-BF16 projections: reserved, SPP_ENOTSUP        */
 } spp_precision;
 
+typedef enum {
+    SPP_PATH_AUTO = 0,     /* fused when the grid allows it, else staged           */
+    SPP_PATH_STAGED = 1,   /* five kernels: FFT, projection, radial, projection, FFT */
+    SPP_PATH_FUSED = 2     /* folded FFT, one per-mode kernel, folded inverse FFT  */
+} spp_path;
+
 typedef struct spp_grid_s* spp_grid;   /* host geometry, immutable        */
 typedef struct spp_plan_s* spp_plan;   /* eigensystems + device layout    */
 typedef struct spp_batch_s* spp_batch; /* captured graph of many solves   */
@@ -182,7 +188,9 @@ spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const d
  *   3 inverse theta projection (MFMA GEMM)
  *   4 inverse real FFT along phi
  * then waits for the last event and writes the stage durations in
- * milliseconds to stage_ms (host, 5 doubles).  Blocks the calling thread.
+ * milliseconds to stage_ms (host, 5 doubles).  On the fused path stage 1
+ * is the per-mode kernel (both projections and the radial solves) and
+ * stages 2 and 3 are empty.  Blocks the calling thread.
  * Errors: as spp_solve, plus SPP_EINVAL for stage_ms == NULL.
  */
 spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev, double G,
@@ -268,6 +276,25 @@ spp_status spp_theta_eigensystem(spp_plan p, int m, double* H, double* lam);
  * N_theta^2 product), else 0.  Errors: SPP_EINVAL.
  */
 spp_status spp_plan_parity_split(spp_plan p, int* on);
+
+/*
+ * Kernel path of the FP64 solves of a plan (spp_solve, spp_solve_profiled,
+ * batches and servers created afterwards).  The fused path applies to
+ * equator-symmetric theta grids (Sec. 4.2) with N_theta % 4 == 0,
+ * N_theta <= 128 and N_r <= 576: the forward FFT stores the even and odd
+ * theta folds s_j +- s_{N-1-j}; one kernel per (Fourier component, parity)
+ * then runs the forward projection, the radial solves of Sec. 3.2 and the
+ * inverse projection with its N_r x N_theta/2 slab held on chip; the
+ * inverse FFT unfolds.  Both paths solve the same discrete system (results
+ * agree to rounding).  The default is SPP_PATH_AUTO.  Not to be changed
+ * while solves of the plan are being enqueued on other threads.
+ * Errors: SPP_EINVAL (NULL, unknown path), SPP_ENOTSUP (SPP_PATH_FUSED for a
+ * grid it does not cover).
+ *   spp_plan_get_path: the path solves take now (SPP_PATH_STAGED or
+ *   SPP_PATH_FUSED).
+ */
+spp_status spp_plan_set_path(spp_plan p, spp_path path);
+spp_status spp_plan_get_path(spp_plan p, spp_path* path);
 
 /* Grid sizes of a plan (any pointer may be NULL). */
 spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi);

@@ -80,6 +80,10 @@ lib.spp_server_destroy.argtypes = [_vp]
 lib.spp_server_destroy.restype = None
 lib.spp_plan_parity_split.argtypes = [_vp, ctypes.POINTER(_c_int)]
 lib.spp_plan_parity_split.restype = _c_int
+lib.spp_plan_set_path.argtypes = [_vp, _c_int]
+lib.spp_plan_set_path.restype = _c_int
+lib.spp_plan_get_path.argtypes = [_vp, ctypes.POINTER(_c_int)]
+lib.spp_plan_get_path.restype = _c_int
 lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
 lib.spp_theta_eigensystem.restype = _c_int
 lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
@@ -148,6 +152,20 @@ class Plan:
             self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
             _check(lib.spp_plan_upload(plan, _vp(self._plan_dev.data_ptr()), _stream_ptr(None)),
                    "spp_plan_upload")
+
+    PATHS = {"auto": 0, "staged": 1, "fused": 2}
+
+    @property
+    def path(self):
+        """Kernel path of the FP64 solves: "staged" (five kernels) or "fused"
+        (folded FFT, one per-mode kernel, folded inverse FFT)."""
+        v = _c_int()
+        _check(lib.spp_plan_get_path(self._plan, ctypes.byref(v)), "spp_plan_get_path")
+        return {1: "staged", 2: "fused"}[v.value]
+
+    @path.setter
+    def path(self, name):
+        _check(lib.spp_plan_set_path(self._plan, self.PATHS[name]), "spp_plan_set_path")
 
     @property
     def parity_split(self):

@@ -1,6 +1,7 @@
 // Internal declarations shared by the host set-up code and the HIP solve path.
 #pragma once
 
+#include <atomic>
 #include <cstddef>
 #include <string>
 #include <vector>
@@ -30,6 +31,8 @@ struct spp_plan_layout {
     size_t Himg32 = 0;
     size_t Wpar = 0;    // parity-split images, [M][2][KMAX][NP] (even, odd)
     size_t Hpar = 0;
+    size_t Fimg = 0;    // fused per-mode kernel images, [M][2][KP][NP] (forward, then inverse)
+    size_t Iimg = 0;
     size_t sig = 0;     // theta face coefficients sigma_{j+1/2}, [N_theta + 1] (poles 0)
     size_t dmu = 0;     // cos theta_{j-1/2} - cos theta_{j+1/2}, [N_theta]
     size_t Sj = 0;      // S_j, [N_theta]
@@ -47,6 +50,9 @@ struct spp_plan_s {
     int proj_rn = 0;                           // tile width of the projection kernel (0: fallback)
     bool parity = false;                       // equator-symmetric theta grid: modes ordered even, odd
     int par_rn = 0;                            // tile width of the parity-split kernel (0: not used)
+    std::vector<double> Fimg, Iimg;            // images of the fused per-mode kernel
+    bool fused_ok = false;                     // the fused per-mode path can run this grid
+    std::atomic<int> path{SPP_PATH_AUTO};      // requested path (spp_plan_set_path)
     spp_plan_layout lay;
     size_t workspace_bytes = 0;
     void* dev = nullptr;                       // caller-owned device copy
@@ -82,5 +88,9 @@ spp_status spp_validate_solve(const char* who, const spp_plan_s* p, const double
 // e[n-1] off-diagonal; on return d holds the eigenvalues in ascending order
 // and Z (row-major n x n) the orthonormal eigenvectors as columns.
 bool spp_tridiag_eigen(int n, std::vector<double>& d, std::vector<double> e, std::vector<double>& Z);
+
+// The solve takes the fused per-mode path (folded FFT, one kernel for
+// projection + radial + inverse projection, folded inverse FFT).
+inline bool spp_plan_fused(const spp_plan_s* p) { return p->fused_ok && p->path.load() != SPP_PATH_STAGED; }
 
 inline size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }

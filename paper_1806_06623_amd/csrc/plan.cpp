@@ -10,6 +10,7 @@
 #include <thread>
 
 #include "internal.h"
+#include "modal_layout.h"
 #include "proj_layout.h"
 
 static thread_local std::string g_last_error;
@@ -163,6 +164,37 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             p->Uo.assign(size_t(nm) * hh * hh, 0.0);
         }
 
+        // No flux crosses the poles (Sec. 3.1), so for m = 0 the theta operator
+        // (and the even half-operator of the parity split) has zero row sums:
+        // the constant is an exact eigenvector with eigenvalue 0, the largest.
+        // It is set exactly -- a computed one is off by about eps |K| / gap,
+        // which the large radial response of this mode carries into Phi --
+        // and the other eigenvectors are made exactly orthogonal to it.  Here
+        // z = D^1/2 h are the eigenvectors of the symmetrised matrix (columns
+        // of the row-major n x n array Z), so the null vector is sqrt(dmu_j).
+        auto exact_null_pair = [&](int n, std::vector<double>& d, std::vector<double>& Z) {
+            int top = 0;
+            for (int l = 1; l < n; ++l)
+                if (d[l] > d[top]) top = l;
+            std::vector<double> c(n);
+            double nc = 0.0;
+            for (int j = 0; j < n; ++j) nc += G.dmu[j];
+            for (int j = 0; j < n; ++j) c[j] = std::sqrt(G.dmu[j] / nc);
+            for (int l = 0; l < n; ++l) {
+                if (l == top) continue;
+                double dot = 0.0, nn = 0.0;
+                for (int j = 0; j < n; ++j) dot += c[j] * Z[size_t(j) * n + l];
+                for (int j = 0; j < n; ++j) {
+                    Z[size_t(j) * n + l] -= dot * c[j];
+                    nn += Z[size_t(j) * n + l] * Z[size_t(j) * n + l];
+                }
+                const double s = 1.0 / std::sqrt(nn);
+                for (int j = 0; j < n; ++j) Z[size_t(j) * n + l] *= s;
+            }
+            for (int j = 0; j < n; ++j) Z[size_t(j) * n + top] = c[j];
+            d[top] = 0.0;
+        };
+
         bool ok = true;
         auto set_lam = [&](int m, int l, double lam) {
             p->lam[size_t(m) * nth + l] = lam;
@@ -189,6 +221,7 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
                         }
                         for (int j = 0; j + 1 < hh; ++j) eh[j] = G.sigma[j + 1] * isd[j] * isd[j + 1];
                         if (!spp_tridiag_eigen(hh, dh, eh, Zh)) { ok = false; return; }
+                        if (m == 0 && par == 0) exact_null_pair(hh, dh, Zh);
                         double* U = &(par == 0 ? p->Ue : p->Uo)[size_t(m) * hh * hh];
                         const double sgn = par == 0 ? 1.0 : -1.0;
                         for (int j = 0; j < hh; ++j)
@@ -210,6 +243,7 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
                            * isd[j] * isd[j];
                 for (int j = 0; j + 1 < nth; ++j) e[j] = G.sigma[j + 1] * isd[j] * isd[j + 1];
                 if (!spp_tridiag_eigen(nth, d, e, Z)) { ok = false; return; }
+                if (m == 0) exact_null_pair(nth, d, Z);
                 for (int j = 0; j < nth; ++j)
                     for (int l = 0; l < nth; ++l) {
                         const double h = Z[size_t(j) * nth + l] * isd[j];   // H = D^-1/2 V
@@ -284,6 +318,31 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
                 }
         }
 
+        // LDS images of the fused per-mode kernel ([m][parity][KP][NP], rows in
+        // the interleaved k order of modal_layout.h):
+        //   forward  B_p[k = j][n = l] = U_p[j][l] dmu_j / sqrt 2
+        //   inverse  B_p[k = l][n = j] = U_p[j][l] / sqrt 2
+        p->fused_ok = symmetric && hh % 2 == 0 && hh <= 64 && nr <= modalimg::NRMAX;
+        if (p->fused_ok) {
+            const int rn = modalimg::rn_for(hh);
+            const size_t ie = modalimg::elems(rn);
+            const int NP = modalimg::np(rn);
+            const double r2 = std::sqrt(0.5);
+            p->Fimg.assign(size_t(nm) * 2 * ie, 0.0);
+            p->Iimg.assign(size_t(nm) * 2 * ie, 0.0);
+            for (int m = 0; m < nm; ++m)
+                for (int par = 0; par < 2; ++par) {
+                    const double* U = &(par == 0 ? p->Ue : p->Uo)[size_t(m) * hh * hh];
+                    const size_t base = (size_t(m) * 2 + par) * ie;
+                    for (int k = 0; k < hh; ++k)
+                        for (int n = 0; n < hh; ++n) {
+                            const size_t dst = base + size_t(modalimg::row_of(k)) * NP + n;
+                            p->Fimg[dst] = U[size_t(k) * hh + n] * G.dmu[k] * r2;
+                            p->Iimg[dst] = U[size_t(n) * hh + k] * r2;
+                        }
+                }
+        }
+
         // device layout
         spp_plan_layout& L = p->lay;
         size_t off = 0;
@@ -311,6 +370,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.Himg32 = take_f(p->Himg32.size());
         L.Wpar = take(p->Wpar.size());
         L.Hpar = take(p->Hpar.size());
+        L.Fimg = take(p->Fimg.size());
+        L.Iimg = take(p->Iimg.size());
         L.sig = take(p->sig.size());
         L.dmu = take(p->dmu.size());
         L.Sj = take(p->Sj.size());
@@ -345,6 +406,26 @@ extern "C" spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi)
     return SPP_OK;
 }
 
+extern "C" spp_status spp_plan_set_path(spp_plan p, spp_path path)
+{
+    if (!p) return spp_fail(SPP_EINVAL, "spp_plan_set_path: NULL plan");
+    if (path != SPP_PATH_AUTO && path != SPP_PATH_STAGED && path != SPP_PATH_FUSED)
+        return spp_fail(SPP_EINVAL, "spp_plan_set_path: unknown path");
+    if (path == SPP_PATH_FUSED && !p->fused_ok)
+        return spp_fail(SPP_ENOTSUP, "spp_plan_set_path: the fused per-mode path needs an equator-symmetric "
+                                     "theta grid with N_theta % 4 == 0, N_theta <= 128 and N_r <= " +
+                                         std::to_string(modalimg::NRMAX));
+    p->path.store(path);
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_plan_get_path(spp_plan p, spp_path* path)
+{
+    if (!p || !path) return spp_fail(SPP_EINVAL, "spp_plan_get_path: NULL pointer");
+    *path = spp_plan_fused(p) ? SPP_PATH_FUSED : SPP_PATH_STAGED;
+    return SPP_OK;
+}
+
 extern "C" spp_status spp_plan_parity_split(spp_plan p, int* on)
 {
     if (!p || !on) return spp_fail(SPP_EINVAL, "spp_plan_parity_split: NULL pointer");
@@ -375,6 +456,8 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     std::memcpy(img.data() + p->lay.Himg32, p->Himg32.data(), p->Himg32.size() * sizeof(float));
     put(p->lay.Wpar, p->Wpar);
     put(p->lay.Hpar, p->Hpar);
+    put(p->lay.Fimg, p->Fimg);
+    put(p->lay.Iimg, p->Iimg);
     put(p->lay.sig, p->sig);
     put(p->lay.dmu, p->dmu);
     put(p->lay.Sj, p->Sj);

@@ -19,6 +19,7 @@
 
 #include "fft.hip.h"
 #include "internal.h"
+#include "modal.hip.h"
 #include "proj.hip.h"
 #include "radial.hip.h"
 
@@ -28,10 +29,14 @@ namespace {
 // Persistent workgroups: each one loops over blocks of JB lines and keeps the
 // global loads of its next block in flight (in registers) while the current
 // block is transformed in LDS.
-template <int N>
+// With FOLD (equator-symmetric theta grids, Sec. 4.2) a block holds JB/2
+// line pairs (i, k), (i, N_theta-1-k), k < h = N_theta/2; it transforms the
+// even fold (sum) and the odd fold (difference) and stores them as lines
+// (i, k) and (i, h+k).
+template <int N, bool FOLD = false>
 __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
                                                   const c64* __restrict__ tw_g, double scale, int nlines,
-                                                  int nblocks)
+                                                  int nblocks, int nth)
 {
     using S = FftShape<N>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
@@ -44,13 +49,28 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
     // end are clamped (those lines are never stored)
     const double2* src = reinterpret_cast<const double2*>(rho);
     const size_t total = size_t(nlines) * N2;
+    constexpr int PB = FOLD ? JB / 2 : JB;       // line pairs (FOLD) or lines per block
+    const int h = nth >> 1;
+    const size_t npairs = size_t(nlines) / 2;
     double2 pre[PER];
     auto prefetch = [&](int blk) {
-        const size_t base = size_t(blk) * JB * N2 + threadIdx.x;
+        if constexpr (FOLD) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const size_t e = base + 256 * u;
-            pre[u] = src[e < total ? e : total - 1];
+            for (int u = 0; u < PER / 2; ++u) {
+                const int e = threadIdx.x + 256 * u;
+                size_t P = size_t(blk) * PB + e / N2;
+                P = P < npairs ? P : npairs - 1;
+                const int i = int(P / h), k = int(P - size_t(i) * h);
+                pre[2 * u] = src[(size_t(i) * nth + k) * N2 + e % N2];
+                pre[2 * u + 1] = src[(size_t(i) * nth + nth - 1 - k) * N2 + e % N2];
+            }
+        } else {
+            const size_t base = size_t(blk) * JB * N2 + threadIdx.x;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const size_t e = base + 256 * u;
+                pre[u] = src[e < total ? e : total - 1];
+            }
         }
     };
 
@@ -60,21 +80,40 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
     int blk = blockIdx.x;
     if (blk < nblocks) prefetch(blk);
     for (; blk < nblocks; blk += gridDim.x) {
+        if constexpr (FOLD) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + 256 * u;
-            lds[(e / N2) * LS + pidx(e % N2)] = {pre[u].x * scale, pre[u].y * scale};
+            for (int u = 0; u < PER / 2; ++u) {
+                const int e = threadIdx.x + 256 * u;
+                const double2 a = pre[2 * u], b = pre[2 * u + 1];
+                lds[(e / N2) * LS + pidx(e % N2)] = {(a.x + b.x) * scale, (a.y + b.y) * scale};
+                lds[(PB + e / N2) * LS + pidx(e % N2)] = {(a.x - b.x) * scale, (a.y - b.y) * scale};
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = threadIdx.x + 256 * u;
+                lds[(e / N2) * LS + pidx(e % N2)] = {pre[u].x * scale, pre[u].y * scale};
+            }
         }
         __syncthreads();
         if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
         fft_passes<N2, 1, T, S::E>(lds + line * LS, tid, tws);
 
         // split Z into the half spectrum X_m and store halfcomplex planes
-        const int L0 = blk * JB;
-        const int nl = min(JB, nlines - L0);
-        if (l < nl) {
+        bool valid;
+        size_t oline;
+        if constexpr (FOLD) {
+            const size_t P = size_t(blk) * PB + (l % PB);
+            valid = P < npairs;
+            const int i = int(P / h), k = int(P - size_t(i) * h);
+            oline = size_t(i) * nth + (l / PB) * h + k;
+        } else {
+            oline = size_t(blk) * JB + l;
+            valid = oline < size_t(nlines);
+        }
+        if (valid) {
             const c64* Z = lds + l * LS;
-            double* out = X + L0 + l;
+            double* out = X + oline;
             for (int p = grp; p <= N2 / 2; p += T) {
                 const c64 a = Z[pidx(p)];
                 const c64 b = Z[pidx((N2 - p) & (N2 - 1))];
@@ -103,9 +142,12 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
     }
 }
 
-template <int N>
+// With FOLD the block's lines are the even and odd folds (i, k), (i, h+k)
+// of JB/2 pairs; it stores their sum as line (i, k) and their difference as
+// line (i, N_theta-1-k).
+template <int N, bool FOLD = false>
 __global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
-                                                  const c64* __restrict__ tw_g, int nlines, int nblocks)
+                                                  const c64* __restrict__ tw_g, int nlines, int nblocks, int nth)
 {
     using S = FftShape<N>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
@@ -121,9 +163,20 @@ __global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, 
 
     // raw halfcomplex values of task p: Re X_p, Im X_p, Re X_{N2-p}, Im X_{N2-p}
     // (for p = 0 the imaginary slots hold Re X_0 and are discarded)
+    constexpr int PB = FOLD ? JB / 2 : JB;
+    const int h = nth >> 1;
+    const size_t npairs = size_t(nlines) / 2;
     double pre[NT][4];
     auto prefetch = [&](int blk) {
-        const int L = min(blk * JB + l, nlines - 1);
+        size_t L;
+        if constexpr (FOLD) {
+            size_t P = size_t(blk) * PB + (l % PB);
+            P = P < npairs ? P : npairs - 1;
+            const int i = int(P / h), k = int(P - size_t(i) * h);
+            L = size_t(i) * nth + (l / PB) * h + k;
+        } else {
+            L = size_t(min(blk * JB + l, nlines - 1));
+        }
         const double* in = X + L;
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
@@ -165,15 +218,31 @@ __global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, 
         fft_passes<N2, 1, T, S::E>(lds + line * LS, tid, tws);
 
         // x_{2n} = Re z_n, x_{2n+1} = Im z_n with z = conj(FFT(conj Z))
-        const int L0 = blk * JB;
-        const int nl = min(JB, nlines - L0);
-        double2* dst = reinterpret_cast<double2*>(phi + size_t(L0) * N);
+        if constexpr (FOLD) {
+            double2* dst = reinterpret_cast<double2*>(phi);
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + 256 * u;
-            if (e < nl * N2) {
-                const c64 v = lds[(e / N2) * LS + pidx(e % N2)];
-                dst[e] = double2{v.x, -v.y};
+            for (int u = 0; u < PER / 2; ++u) {
+                const int e = threadIdx.x + 256 * u;
+                const size_t P = size_t(blk) * PB + e / N2;
+                if (P < npairs) {
+                    const int i = int(P / h), k = int(P - size_t(i) * h);
+                    const c64 ve = lds[(e / N2) * LS + pidx(e % N2)];
+                    const c64 vo = lds[(PB + e / N2) * LS + pidx(e % N2)];
+                    dst[(size_t(i) * nth + k) * N2 + e % N2] = double2{ve.x + vo.x, -(ve.y + vo.y)};
+                    dst[(size_t(i) * nth + nth - 1 - k) * N2 + e % N2] = double2{ve.x - vo.x, -(ve.y - vo.y)};
+                }
+            }
+        } else {
+            const int L0 = blk * JB;
+            const int nl = min(JB, nlines - L0);
+            double2* dst = reinterpret_cast<double2*>(phi + size_t(L0) * N);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = threadIdx.x + 256 * u;
+                if (e < nl * N2) {
+                    const c64 v = lds[(e / N2) * LS + pidx(e % N2)];
+                    dst[e] = double2{v.x, -v.y};
+                }
             }
         }
         __syncthreads();
@@ -435,6 +504,35 @@ bool launch_radial_part(double* Y, const double* lam, const double* beta, const 
     return false;
 }
 
+// Fused per-mode kernel (projection, radial solves, inverse projection) on
+// the folded spectrum X, in place; false when the grid is outside its range.
+bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* lam, const double* beta,
+                  const radial::Coef& cf, int nr, int nth, int nphi, hipStream_t s)
+{
+    const int h = nth / 2;
+    const int rn = modalimg::rn_for(h);
+    const int T = (nr + 16 * modal::NW - 1) / (16 * modal::NW);
+    if (h % 2 != 0 || h > 64 || T < 1 || T > modalimg::TMAX) return false;
+    const dim3 grid(2, nphi), block(modal::THREADS);
+#define SPP_MODAL(RN, TT)                                                                                      \
+    case RN * 4 + TT:                                                                                          \
+        hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, lam, beta, cf, nth, nphi); \
+        return true;
+    switch (rn * 4 + T) {
+        SPP_MODAL(1, 1)
+        SPP_MODAL(1, 2)
+        SPP_MODAL(1, 3)
+        SPP_MODAL(2, 1)
+        SPP_MODAL(2, 2)
+        SPP_MODAL(2, 3)
+        SPP_MODAL(4, 1)
+        SPP_MODAL(4, 2)
+        SPP_MODAL(4, 3)
+    }
+#undef SPP_MODAL
+    return false;
+}
+
 // Workgroups of the FFT kernel for N that fit on the device at once (cached).
 template <int N>
 int fft_resident(bool forward)
@@ -444,9 +542,9 @@ int fft_resident(bool forward)
     if (res == 0) {
         int per_cu = 0;
         if (forward)
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_fwd<N>, 256, 0);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_fwd<N, false>, 256, 0);
         else
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_inv<N>, 256, 0);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_inv<N, false>, 256, 0);
         res = (per_cu > 0 ? per_cu : 1) * device_cus();
     }
     return res;
@@ -454,26 +552,40 @@ int fft_resident(bool forward)
 
 template <int N>
 void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
-                     hipStream_t s)
+                     bool fold, int nth, hipStream_t s)
 {
     using S = FftShape<N>;
-    const int nblocks = (nlines + S::JB - 1) / S::JB;
+    const int per_block = fold ? S::JB / 2 : S::JB;
+    const int units = fold ? nlines / 2 : nlines;
+    const int nblocks = (units + per_block - 1) / per_block;
     // persistent grid: as many workgroups as can be resident, blocks spread evenly
     const int res = fft_resident<N>(forward);
     const int per = (nblocks + res - 1) / res;
     const int grid = (nblocks + per - 1) / per;
-    if (forward)
-        hipLaunchKernelGGL(k_rfft_fwd<N>, dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines, nblocks);
-    else
-        hipLaunchKernelGGL(k_rfft_inv<N>, dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks);
+    if (forward) {
+        if (fold)
+            hipLaunchKernelGGL((k_rfft_fwd<N, true>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
+                               nblocks, nth);
+        else
+            hipLaunchKernelGGL((k_rfft_fwd<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
+                               nblocks, nth);
+    } else {
+        if (fold)
+            hipLaunchKernelGGL((k_rfft_inv<N, true>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
+                               nth);
+        else
+            hipLaunchKernelGGL((k_rfft_inv<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
+                               nth);
+    }
 }
 
+// fold: the line-pair layout of the fused per-mode path (equator-symmetric grids)
 bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
-                hipStream_t s)
+                hipStream_t s, bool fold = false, int nth = 0)
 {
     switch (nphi) {
 #define SPP_FFT_CASE(n) \
-    case n: launch_fft_pair<n>(forward, in, out, tw, scale, nlines, s); return true;
+    case n: launch_fft_pair<n>(forward, in, out, tw, scale, nlines, fold, nth, s); return true;
         SPP_FFT_CASE(4)
         SPP_FFT_CASE(8)
         SPP_FFT_CASE(16)
@@ -629,6 +741,24 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], s);
     };
+    if (spp_plan_fused(p)) {
+        const double* Fimg = reinterpret_cast<const double*>(base + p->lay.Fimg);
+        const double* Iimg = reinterpret_cast<const double*>(base + p->lay.Iimg);
+        mark(0);
+        if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s, true, nth))
+            return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
+        mark(1);
+        if (!launch_modal(X, Fimg, Iimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, s))
+            return spp_fail(SPP_ENOTSUP, "spp_solve: grid outside the fused kernel's range");
+        mark(2);
+        mark(3);
+        mark(4);
+        launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s, true, nth);
+        mark(5);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve: ") + hipGetErrorString(e));
+        return SPP_OK;
+    }
     mark(0);
     if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s))
         return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
