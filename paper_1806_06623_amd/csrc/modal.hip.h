@@ -48,6 +48,11 @@ constexpr int THREADS = 64 * NW;
 constexpr int P = 4 * NW;          // radial partitions per column
 constexpr int TP = 34;             // pitch of the transpose buffer (32 columns + pad)
 
+// Every phase of the kernel is straight-line code in one basic block; this
+// keeps the instruction scheduler from interleaving neighbouring phases
+// (which would keep values of several phases live at once and spill).
+#define MODAL_PHASE_FENCE() __builtin_amdgcn_sched_barrier(0)
+
 template <int RN> struct Geo {
     static constexpr int KP = modalimg::kp(RN);
     static constexpr int KG = KP / 4;        // MFMA steps per tile
@@ -118,13 +123,19 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     constexpr int CH = 4 * T;               // rows per lane chunk
     constexpr int ROWS = NW * 16 * T;       // row capacity
     constexpr int NCH = T * NC;             // load chunks of the forward product
-    constexpr int RED = 10 * P * 16;        // own[3], nxt[3], red[4] of [P][16]
+    constexpr int PS = P * 16;              // one reduced-system field: [P][16]
+    constexpr int RED = 14 * PS;            // own[3], nxt[3], two buffers of red[4]
     constexpr int TRB = NW * 16 * TP;       // one 16 x 32 transpose buffer per wave
     constexpr int UN = RED > TRB ? RED : TRB;
     __shared__ __attribute__((aligned(16))) double Bs[ELEMS];
     __shared__ __attribute__((aligned(16))) double un[UN];
-    __shared__ double xs[(P + 1) * 16];
-    __shared__ double c_alpha[ROWS], c_VR[ROWS], c_V[ROWS];
+    __shared__ double xs[P * 16];
+    // per-row radial coefficients {-(alpha_{i-1} + alpha_i), V_i R_i, [i = N_r - 1],
+    // alpha_i}, so that the diagonal for eigenvalue lambda and outer coefficient
+    // beta is x + y lambda - z beta; rows >= N_r are decoupled identity rows
+    __shared__ double4 t_row[ROWS];
+    __shared__ double t_V[ROWS];
+    __shared__ double t_lam[16 * RN], t_bo[16 * RN];   // lambda_l, beta_l of this (m, parity)
 
     const int par = blockIdx.x, q = blockIdx.y;
     const int m = q <= nphi / 2 ? q : nphi - q;
@@ -150,11 +161,19 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     if constexpr (NCH > 1) load_a(bb, arow(1 / NC), 1 % NC, g, h);
 
     stage_image<ELEMS>(Bs, Fimg + (size_t(m) * 2 + par) * ELEMS);
+    // row i: diagonal without the lambda term -(alpha_{i-1} + alpha_i), V_i R_i,
+    // coupling alpha_i to row i+1 (alpha_{N_r-1} = 0), V_i
+    if (threadIdx.x < 16 * RN) {
+        const int l = threadIdx.x, L = par * h + (l < h ? l : h - 1);
+        t_lam[l] = lam[size_t(m) * nth + L];
+        t_bo[l] = beta[size_t(m) * nth + L];
+    }
     for (int i = threadIdx.x; i < ROWS; i += THREADS) {
         const bool in = i < nr;
-        c_alpha[i] = in ? tab.alpha[i] : 0.0;
-        c_VR[i] = in ? tab.VR[i] : 0.0;
-        c_V[i] = in ? tab.V[i] : 0.0;
+        const double a = in ? tab.alpha[i] : 0.0;
+        const double am = (in && i > 0) ? tab.alpha[i - 1] : 0.0;
+        t_row[i] = double4{in ? -(am + a) : 1.0, in ? tab.VR[i] : 0.0, i == nr - 1 ? 1.0 : 0.0, a};
+        t_V[i] = in ? tab.V[i] : 0.0;
     }
     __syncthreads();
 
@@ -170,176 +189,184 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         }
     }
 
-    // ---- radial solves (partition method on the accumulators)
-    // lane group g of wave w owns rows s0 .. s0 + CH - 1 of its columns
-    const int p = 4 * w + g;
-    const int PA = (nr + CH - 1) / CH;       // partitions that hold rows
-    const bool active = p < PA;
-    const int s0 = p * CH;
-    const int s1 = active ? (s0 + CH < nr ? s0 + CH : nr) : s0 + 1;
-    const int n = s1 - s0 - 1;                // interior rows s0+1 .. s1-1
-    const bool last = p == PA - 1;
-    const radial::RowCoef cf{c_alpha, c_VR, nr};
-#define D(k) acc[(k) >> 2][cb][(k) & 3]
-
+    MODAL_PHASE_FENCE();
+    // ---- radial solves (partition method on the accumulators, no branches:
+    // padding rows have diagonal 1, no coupling and a zero right-hand side,
+    // and partitions past the last row reduce to identity rows)
+    const int p = 4 * w + g;                 // partition of this lane group
+    const int s0 = p * CH;                   // its rows s0 .. s0 + CH - 1
+    // the slab as scalars from here on (no MFMA register tuples to maintain)
+    double sl[T][RN][4];
 #pragma unroll
-    for (int cb = 0; cb < RN; ++cb)
+    for (int rb = 0; rb < T; ++rb)
 #pragma unroll
-        for (int k = 0; k < CH; ++k)
-            if (k <= n) D(k) *= c_V[s0 + k];
+        for (int cb = 0; cb < RN; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sl[rb][cb][v] = acc[rb][cb][v];
+#define D(k) sl[(k) >> 2][cb][(k) & 3]
 
     double* own = un;                 // [3][P][16]
-    double* nxt = un + 3 * P * 16;    // [3][P][16]
-    double* red = un + 6 * P * 16;    // [4][P][16]
-    const double oL = (active && s0 + 1 < nr) ? cf.off(s0) : 0.0;   // s0 <-> s0+1
-    const double oR = (active && !last) ? cf.off(s1 - 1) : 0.0;     // s1-1 <-> s1
+    double* nxt = un + 3 * PS;        // [3][P][16]
+    const double oL = t_row[s0].w;            // s0 <-> s0+1
+    const double oR = t_row[s0 + CH - 1].w;   // last row of the chunk <-> next separator
+    const int pm = p > 0 ? p - 1 : 0;
+    const int pp = p < P - 1 ? p + 1 : P - 1;
 
 #pragma unroll
     for (int cb = 0; cb < RN; ++cb) {
-        const int l = lr + 16 * cb;
-        const int L = par * h + (l < h ? l : h - 1);
-        const double lm = lam[size_t(m) * nth + L];
-        const double bo = beta[size_t(m) * nth + L];
+        MODAL_PHASE_FENCE();
+        const double lm = t_lam[lr + 16 * cb];
+        const double bo = t_bo[lr + 16 * cb];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) D(k) *= t_V[s0 + k];
+        // Row records are read one row ahead: the empty asm statements take the
+        // previous row's pivot as input, which pins the load of row k+1 after
+        // the pivot of row k-1 and the first use of row k after the pivot of
+        // row k-1, so the load latency overlaps one row of the recurrence and
+        // the records of the other rows are never live at the same time.
+        int rb0 = s0;
+#define ROW(k) t_row[rb0 + (k)]
+#define DIAG(r) ((r).x + (r).y * lm - (r).z * bo)
+#define TIE(r, dep) asm volatile("" : "+v"((r).x), "+v"((r).y), "+v"((r).z), "+v"((r).w) : "v"(dep))
+#define NEXT_BASE(dep) asm volatile("" : "+v"(rb0) : "v"(dep))
 
-        // pass 1: eliminate the interior in both directions
+        // pass 1, forward: pivots of rows 1 .. CH-1; last interior row in terms of
+        // the separators (only the previous pivot is kept)
+        double4 cur = ROW(1);
+        double4 nx = ROW(2);
+        double iw = radial::recip(DIAG(cur));
+        double z = D(1), u = -oL, al_prev = cur.w;
+#pragma unroll
+        for (int k = 2; k < CH; ++k) {
+            cur = nx;
+            TIE(cur, iw);
+            NEXT_BASE(iw);
+            if (k + 1 < CH) nx = ROW(k + 1);
+            const double mult = al_prev * iw;
+            iw = radial::recip(DIAG(cur) - mult * al_prev);
+            z = D(k) - mult * z;
+            u = -mult * u;
+            al_prev = cur.w;
+        }
+        // contribution of this chunk to the next separator row
+        nxt[(0 * P + p) * 16 + lr] = oR * (u * iw);
+        nxt[(1 * P + p) * 16 + lr] = oR * (-oR * iw);
+        nxt[(2 * P + p) * 16 + lr] = oR * (z * iw);
+
+        // pass 1, backward: first interior row in terms of the separators
+        NEXT_BASE(iw);
+        cur = ROW(CH - 1);
+        nx = ROW(CH - 2);
+        double iwh = radial::recip(DIAG(cur));
+        double zh = D(CH - 1), vh = -oR;
+#pragma unroll
+        for (int k = CH - 2; k >= 1; --k) {
+            cur = nx;
+            TIE(cur, iwh);
+            NEXT_BASE(iwh);
+            if (k > 1) nx = ROW(k - 1);
+            const double mult = cur.w * iwh;
+            iwh = radial::recip(DIAG(cur) - mult * cur.w);
+            zh = D(k) - mult * zh;
+            vh = -mult * vh;
+        }
+        const double Yf = zh * iwh, Vf = vh * iwh, Uf = -oL * iwh;
+
+        // reduced system over the separators (one row per partition, 16 columns)
+        own[(0 * P + p) * 16 + lr] = DIAG(t_row[s0]) + oL * Uf;
+        own[(1 * P + p) * 16 + lr] = oL * Vf;
+        own[(2 * P + p) * 16 + lr] = D(0) - oL * Yf;
+        __syncthreads();
+        MODAL_PHASE_FENCE();
+        const bool top = p == 0;
+        double rA = top ? 0.0 : nxt[(0 * P + pm) * 16 + lr];
+        double rB = own[(0 * P + p) * 16 + lr] + (top ? 0.0 : nxt[(1 * P + pm) * 16 + lr]);
+        double rC = own[(1 * P + p) * 16 + lr];
+        double rD = own[(2 * P + p) * 16 + lr] - (top ? 0.0 : nxt[(2 * P + pm) * 16 + lr]);
+        // parallel cyclic reduction: after the level of stride hs every row
+        // couples only to rows 2 hs away.  A row with no partner that far has a
+        // zero coupling on that side, so the clamped partner contributes 0.
+        // Two row buffers alternate, one barrier per level.
+#pragma unroll
+        for (int lvl = 0; (1 << lvl) < P; ++lvl) {
+            const int hs = 1 << lvl;
+            double* red = un + 6 * PS + (lvl & 1) * 4 * PS;
+            red[(0 * P + p) * 16 + lr] = rA;
+            red[(1 * P + p) * 16 + lr] = rB;
+            red[(2 * P + p) * 16 + lr] = rC;
+            red[(3 * P + p) * 16 + lr] = rD;
+            __syncthreads();
+            MODAL_PHASE_FENCE();
+            // partner rows, recomputed per level (a copy of p laundered through an
+            // empty asm, so the twelve partner addresses are not all kept live)
+            int pl = p;
+            asm volatile("" : "+v"(pl));
+            const int pa = pl >= hs ? pl - hs : 0;
+            const int pc = pl + hs < P ? pl + hs : P - 1;
+            const double a = -rA * radial::recip(red[(1 * P + pa) * 16 + lr]);
+            const double c = -rC * radial::recip(red[(1 * P + pc) * 16 + lr]);
+            const double nb = rB + a * red[(2 * P + pa) * 16 + lr] + c * red[(0 * P + pc) * 16 + lr];
+            const double nd = rD + a * red[(3 * P + pa) * 16 + lr] + c * red[(3 * P + pc) * 16 + lr];
+            rA = a * red[(0 * P + pa) * 16 + lr];
+            rC = c * red[(2 * P + pc) * 16 + lr];
+            rB = nb;
+            rD = nd;
+        }
+        xs[p * 16 + lr] = rD * radial::recip(rB);
+        __syncthreads();
+        MODAL_PHASE_FENCE();
+
+        // pass 2: interior with both separators known (pivots recomputed)
+        const double xL = xs[p * 16 + lr];
+        const double xR = xs[pp * 16 + lr];     // multiplied by oR = 0 for the last partition
+        D(0) = xL;
+        D(1) -= oL * xL;
+        D(CH - 1) -= oR * xR;
         double invw[CH];
-        double Yf = 0.0, Uf = 0.0, Vf = 1.0, Yl = 0.0, Ul = 1.0, Vl = 0.0;
-        if (active && n >= 1) {
-            double wv = 1.0, zf = 0.0, uf = 0.0, iwn = 0.0;
+        NEXT_BASE(xL);
+        cur = ROW(1);
+        nx = ROW(2);
+        invw[1] = radial::recip(DIAG(cur));
+        al_prev = cur.w;
 #pragma unroll
-            for (int k = 1; k < CH; ++k) {
-                invw[k] = 0.0;
-                if (k <= n) {
-                    const int i = s0 + k;
-                    if (k == 1) {
-                        wv = cf.diag(i, lm, bo);
-                        zf = D(1);
-                        uf = -oL;
-                    } else {
-                        const double o = cf.off(i - 1);
-                        const double mult = o * invw[k - 1];
-                        wv = cf.diag(i, lm, bo) - mult * o;
-                        zf = D(k) - mult * zf;
-                        uf = -mult * uf;
-                    }
-                    invw[k] = radial::recip(wv);
-                    iwn = invw[k];
-                }
-            }
-            Yl = zf * iwn;
-            Ul = uf * iwn;
-            Vl = -oR * iwn;
-            double wh = 1.0, zh = 0.0, vh = 0.0, iwh = 0.0;
+        for (int k = 2; k < CH; ++k) {
+            cur = nx;
+            TIE(cur, invw[k - 1]);
+            NEXT_BASE(invw[k - 1]);
+            if (k + 1 < CH) nx = ROW(k + 1);
+            const double mult = al_prev * invw[k - 1];
+            invw[k] = radial::recip(DIAG(cur) - mult * al_prev);
+            D(k) -= mult * D(k - 1);
+            al_prev = cur.w;
+        }
+        // back substitution; alpha of row k is al(k), read one row ahead
+        double xn = D(CH - 1) * invw[CH - 1];
+        D(CH - 1) = xn;
+        NEXT_BASE(xn);
+        double an = t_row[rb0 + CH - 2].w;
 #pragma unroll
-            for (int k = CH - 1; k >= 1; --k) {
-                if (k <= n) {
-                    const int i = s0 + k;
-                    if (k == n) {
-                        wh = cf.diag(i, lm, bo);
-                        zh = D(k);
-                        vh = -oR;
-                    } else {
-                        const double o = cf.off(i);
-                        const double mult = o * iwh;
-                        wh = cf.diag(i, lm, bo) - mult * o;
-                        zh = D(k) - mult * zh;
-                        vh = -mult * vh;
-                    }
-                    iwh = radial::recip(wh);
-                }
-            }
-            Yf = zh * iwh;
-            Vf = vh * iwh;
-            Uf = -oL * iwh;
+        for (int k = CH - 2; k >= 1; --k) {
+            double ak = an;
+            asm volatile("" : "+v"(ak) : "v"(xn));
+            NEXT_BASE(xn);
+            if (k > 1) an = t_row[rb0 + k - 1].w;
+            xn = (D(k) - ak * xn) * invw[k];
+            D(k) = xn;
         }
-
-        // reduced system over the separators s_0 .. s_{PA-1} of these 16 columns
-        if (active) {
-            const double bs = cf.diag(s0, lm, bo);
-            own[(0 * P + p) * 16 + lr] = bs + oL * Uf;
-            own[(1 * P + p) * 16 + lr] = oL * Vf;
-            own[(2 * P + p) * 16 + lr] = D(0) - oL * Yf;
-            nxt[(0 * P + p) * 16 + lr] = oR * Ul;
-            nxt[(1 * P + p) * 16 + lr] = oR * Vl;
-            nxt[(2 * P + p) * 16 + lr] = oR * Yl;
-        }
-        __syncthreads();
-        double rA = 0.0, rB = 1.0, rC = 0.0, rD = 0.0;
-        if (active) {
-            rB = own[(0 * P + p) * 16 + lr];
-            rC = own[(1 * P + p) * 16 + lr];
-            rD = own[(2 * P + p) * 16 + lr];
-            if (p > 0) {
-                rA = nxt[(0 * P + p - 1) * 16 + lr];
-                rB += nxt[(1 * P + p - 1) * 16 + lr];
-                rD -= nxt[(2 * P + p - 1) * 16 + lr];
-            }
-        }
-        // parallel cyclic reduction: after step hs every row couples only to
-        // rows 2 hs away; rows outside 0 .. PA-1 are absent
-        for (int hs = 1; hs < PA; hs *= 2) {
-            if (active) {
-                red[(0 * P + p) * 16 + lr] = rA;
-                red[(1 * P + p) * 16 + lr] = rB;
-                red[(2 * P + p) * 16 + lr] = rC;
-                red[(3 * P + p) * 16 + lr] = rD;
-            }
-            __syncthreads();
-            if (active) {
-                double nb = rB, nd = rD, na = 0.0, nc = 0.0;
-                if (p >= hs) {
-                    const double a = -rA * radial::recip(red[(1 * P + p - hs) * 16 + lr]);
-                    na = a * red[(0 * P + p - hs) * 16 + lr];
-                    nb += a * red[(2 * P + p - hs) * 16 + lr];
-                    nd += a * red[(3 * P + p - hs) * 16 + lr];
-                }
-                if (p + hs < PA) {
-                    const double c = -rC * radial::recip(red[(1 * P + p + hs) * 16 + lr]);
-                    nc = c * red[(2 * P + p + hs) * 16 + lr];
-                    nb += c * red[(0 * P + p + hs) * 16 + lr];
-                    nd += c * red[(3 * P + p + hs) * 16 + lr];
-                }
-                rA = na;
-                rB = nb;
-                rC = nc;
-                rD = nd;
-            }
-            __syncthreads();
-        }
-        if (active) xs[p * 16 + lr] = rD * radial::recip(rB);
-        __syncthreads();
-
-        // pass 2: interior with both separators known
-        if (active) {
-            const double xL = xs[p * 16 + lr];
-            const double xR = last ? 0.0 : xs[(p + 1) * 16 + lr];
-            D(0) = xL;
-            if (n >= 1) {
-                D(1) -= oL * xL;
-#pragma unroll
-                for (int k = 1; k < CH; ++k)
-                    if (k == n) D(k) -= oR * xR;
-#pragma unroll
-                for (int k = 2; k < CH; ++k)
-                    if (k <= n) D(k) -= cf.off(s0 + k - 1) * invw[k - 1] * D(k - 1);
-                double xn = 0.0;
-#pragma unroll
-                for (int k = CH - 1; k >= 1; --k) {
-                    if (k <= n) {
-                        const double up = k < n ? cf.off(s0 + k) * xn : 0.0;
-                        xn = (D(k) - up) * invw[k];
-                        D(k) = xn;
-                    }
-                }
-            }
-        }
+#undef ROW
+#undef DIAG
+#undef TIE
+#undef NEXT_BASE
     }
 #undef D
 
-    // ---- inverse projection, tile by tile through the transpose buffer
-    __syncthreads();   // every wave is done with the forward image and the reduced system
+    // ---- inverse projection, tile by tile through a per-wave transpose
+    // buffer (wave-local ordering only: LDS operations of one wave complete
+    // in order, and the fences keep the compiler from reordering them)
+    MODAL_PHASE_FENCE();
     stage_image<ELEMS>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS);
     __syncthreads();
+    MODAL_PHASE_FENCE();
     double* tb = un + w * 16 * TP;
 #pragma unroll
     for (int rb = 0; rb < T; ++rb) {
@@ -348,15 +375,18 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         for (int cb = 0; cb < RN; ++cb) out[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < NC; ++kc) {
+            MODAL_PHASE_FENCE();
             // columns 32 kc .. 32 kc + 31 of tile rb, row r = g + 4 v
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int cb = 2 * kc + half;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    tb[(g + 4 * v) * TP + lr + 16 * half] = cb < RN ? acc[rb][cb < RN ? cb : 0][v] : 0.0;
+                    tb[(g + 4 * v) * TP + lr + 16 * half] = cb < RN ? sl[rb][cb < RN ? cb : 0][v] : 0.0;
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             double a[8];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -364,7 +394,9 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
                 a[2 * t] = x.x;
                 a[2 * t + 1] = x.y;
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             mma_chunk<RN>(out, a, Bs, kc, g, lr);
         }
 #pragma unroll
