@@ -118,10 +118,10 @@ __device__ __forceinline__ void fft_passes(c64* line, int tid, const c64* __rest
 }
 
 // Thread/line mapping of the FFT kernels for a given N = N_phi.
-template <int N> struct FftShape {
+template <int N, int THREADS_ = 256> struct FftShape {
     static constexpr int N2 = N / 2;                 // complex points per line
     static constexpr int E = N2 < 8 ? N2 : 8;        // complex values per thread
     static constexpr int T = N2 / E;                 // threads per line
-    static constexpr int THREADS = 256;
+    static constexpr int THREADS = THREADS_;
     static constexpr int JB = THREADS / T;           // lines per workgroup
 };

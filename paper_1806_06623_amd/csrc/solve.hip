@@ -34,16 +34,17 @@ namespace {
 // even fold (sum) and the odd fold (difference) and stores them as lines
 // (i, k) and (i, h+k).
 template <int N, bool FOLD = false>
-__global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
+__global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
                                                   const c64* __restrict__ tw_g, double scale, int nlines,
                                                   int nblocks, int nth)
 {
-    using S = FftShape<N>;
+    constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
+    using S = FftShape<N, TH>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
-    constexpr int PER = JB * N2 / 256;           // complex values loaded per thread and block
+    constexpr int PER = JB * N2 / TH;           // complex values loaded per thread and block
     __shared__ c64 lds[JB * LS];
     __shared__ c64 tws[N];
-    for (int t = threadIdx.x; t < N; t += 256) tws[t] = tw_g[t];
+    for (int t = threadIdx.x; t < N; t += TH) tws[t] = tw_g[t];
 
     // a real line of N doubles is read as N2 complex values; indices past the
     // end are clamped (those lines are never stored)
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
         if constexpr (FOLD) {
 #pragma unroll
             for (int u = 0; u < PER / 2; ++u) {
-                const int e = threadIdx.x + 256 * u;
+                const int e = threadIdx.x + TH * u;
                 size_t P = size_t(blk) * PB + e / N2;
                 P = P < npairs ? P : npairs - 1;
                 const int i = int(P / h), k = int(P - size_t(i) * h);
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
             const size_t base = size_t(blk) * JB * N2 + threadIdx.x;
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const size_t e = base + 256 * u;
+                const size_t e = base + TH * u;
                 pre[u] = src[e < total ? e : total - 1];
             }
         }
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
         if constexpr (FOLD) {
 #pragma unroll
             for (int u = 0; u < PER / 2; ++u) {
-                const int e = threadIdx.x + 256 * u;
+                const int e = threadIdx.x + TH * u;
                 const double2 a = pre[2 * u], b = pre[2 * u + 1];
                 lds[(e / N2) * LS + pidx(e % N2)] = {(a.x + b.x) * scale, (a.y + b.y) * scale};
                 lds[(PB + e / N2) * LS + pidx(e % N2)] = {(a.x - b.x) * scale, (a.y - b.y) * scale};
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
         } else {
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const int e = threadIdx.x + 256 * u;
+                const int e = threadIdx.x + TH * u;
                 lds[(e / N2) * LS + pidx(e % N2)] = {pre[u].x * scale, pre[u].y * scale};
             }
         }
@@ -146,16 +147,17 @@ __global__ __launch_bounds__(256) void k_rfft_fwd(const double* __restrict__ rho
 // of JB/2 pairs; it stores their sum as line (i, k) and their difference as
 // line (i, N_theta-1-k).
 template <int N, bool FOLD = false>
-__global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
+__global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
                                                   const c64* __restrict__ tw_g, int nlines, int nblocks, int nth)
 {
-    using S = FftShape<N>;
+    constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
+    using S = FftShape<N, TH>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
     constexpr int NT = (N2 / 2 + T) / T;         // split tasks p = 0..N2/2 per thread
-    constexpr int PER = JB * N2 / 256;
+    constexpr int PER = JB * N2 / TH;
     __shared__ c64 lds[JB * LS];
     __shared__ c64 tws[N];
-    for (int t = threadIdx.x; t < N; t += 256) tws[t] = tw_g[t];
+    for (int t = threadIdx.x; t < N; t += TH) tws[t] = tw_g[t];
 
     const int line = threadIdx.x / T, tid = threadIdx.x % T;
     const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, 
             double2* dst = reinterpret_cast<double2*>(phi);
 #pragma unroll
             for (int u = 0; u < PER / 2; ++u) {
-                const int e = threadIdx.x + 256 * u;
+                const int e = threadIdx.x + TH * u;
                 const size_t P = size_t(blk) * PB + e / N2;
                 if (P < npairs) {
                     const int i = int(P / h), k = int(P - size_t(i) * h);
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(256) void k_rfft_inv(const double* __restrict__ X, 
             double2* dst = reinterpret_cast<double2*>(phi + size_t(L0) * N);
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const int e = threadIdx.x + 256 * u;
+                const int e = threadIdx.x + TH * u;
                 if (e < nl * N2) {
                     const c64 v = lds[(e / N2) * LS + pidx(e % N2)];
                     dst[e] = double2{v.x, -v.y};
@@ -535,14 +537,18 @@ bool launch_modal(double* X, const double* Fimg, const double* Iimg, const doubl
 
 // Workgroups of the FFT kernel for N that fit on the device at once (cached).
 template <int N>
-int fft_resident(bool forward)
+int fft_resident(bool forward, bool fold)
 {
-    static int resident[2] = {0, 0};
-    int& res = resident[forward ? 0 : 1];
+    static int resident[4] = {0, 0, 0, 0};
+    int& res = resident[(forward ? 0 : 1) + (fold ? 2 : 0)];
     if (res == 0) {
         int per_cu = 0;
-        if (forward)
+        if (forward && fold)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_fwd<N, true>, 512, 0);
+        else if (forward)
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_fwd<N, false>, 256, 0);
+        else if (fold)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_inv<N, true>, 512, 0);
         else
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rfft_inv<N, false>, 256, 0);
         res = (per_cu > 0 ? per_cu : 1) * device_cus();
@@ -554,24 +560,23 @@ template <int N>
 void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
                      bool fold, int nth, hipStream_t s)
 {
-    using S = FftShape<N>;
-    const int per_block = fold ? S::JB / 2 : S::JB;
+    const int per_block = fold ? FftShape<N, 512>::JB / 2 : FftShape<N, 256>::JB;
     const int units = fold ? nlines / 2 : nlines;
     const int nblocks = (units + per_block - 1) / per_block;
     // persistent grid: as many workgroups as can be resident, blocks spread evenly
-    const int res = fft_resident<N>(forward);
+    const int res = fft_resident<N>(forward, fold);
     const int per = (nblocks + res - 1) / res;
     const int grid = (nblocks + per - 1) / per;
     if (forward) {
         if (fold)
-            hipLaunchKernelGGL((k_rfft_fwd<N, true>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
+            hipLaunchKernelGGL((k_rfft_fwd<N, true>), dim3(grid), dim3(512), 0, s, in, out, tw, scale, nlines,
                                nblocks, nth);
         else
             hipLaunchKernelGGL((k_rfft_fwd<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
                                nblocks, nth);
     } else {
         if (fold)
-            hipLaunchKernelGGL((k_rfft_inv<N, true>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
+            hipLaunchKernelGGL((k_rfft_inv<N, true>), dim3(grid), dim3(512), 0, s, in, out, tw, nlines, nblocks,
                                nth);
         else
             hipLaunchKernelGGL((k_rfft_inv<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
@@ -897,7 +902,11 @@ void spp_prewarm_launch_caches(const spp_plan_s* p)
 {
     (void)device_cus();
     switch (p->nphi) {
-#define SPP_WARM(n) case n: fft_resident<n>(true); fft_resident<n>(false); break;
+#define SPP_WARM(n)                                                                                    \
+    case n:                                                                                            \
+        fft_resident<n>(true, false); fft_resident<n>(false, false);                                   \
+        fft_resident<n>(true, true); fft_resident<n>(false, true);                                     \
+        break;
         SPP_WARM(4) SPP_WARM(8) SPP_WARM(16) SPP_WARM(32) SPP_WARM(64)
         SPP_WARM(128) SPP_WARM(256) SPP_WARM(512) SPP_WARM(1024) SPP_WARM(2048)
 #undef SPP_WARM
