@@ -27,24 +27,34 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 matrix, TFLOP/s
 STAGES = ["fft_forward", "projection_forward", "radial_tridiagonal", "projection_inverse", "fft_inverse"]
-METRIC = "solves/s & Gzones/s at 550×128×256 (FP64 vs mixed); p50/p99 latency"
+FUSED_STAGES = ["fft_forward", "fused_modal", "fft_inverse"]
+METRIC = "solves/s & Gzones/s at 550\u00d7128\u00d7256 (FP64 vs mixed); p50/p99 latency"
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_model(nr, nth, nphi, parity):
+def stage_model(nr, nth, nphi, parity, fused):
     """Algorithmic bytes and flops per launch of each stage (FP64).
 
     With the parity split each N_theta^2 product per Fourier component becomes
-    two (N_theta/2)^2 products: half the flops and half the matrix bytes.
+    two (N_theta/2)^2 products: half the flops and half the matrix bytes.  The
+    fused per-mode kernel reads the folded spectrum once, writes the result
+    once and runs both products (the radial solves' few flops per value are
+    not counted).
     """
     n = nr * nth * nphi
     field = 8.0 * n                                   # one real field, bytes
     nm = nphi // 2 + 1
     basis = 8.0 * nm * nth * nth * (0.5 if parity else 1.0)
     proj_flops = 2.0 * nr * nth * nth * nphi * (0.5 if parity else 1.0)
+    if fused:
+        return {
+            "fft_forward": {"bytes": 2 * field, "flops": None},
+            "fused_modal": {"bytes": 2 * field + 2 * basis, "flops": 2 * proj_flops},
+            "fft_inverse": {"bytes": 2 * field, "flops": None},
+        }
     return {
         "fft_forward": {"bytes": 2 * field, "flops": None},
         "projection_forward": {"bytes": 2 * field + basis, "flops": proj_flops},
@@ -55,25 +65,26 @@ def stage_model(nr, nth, nphi, parity):
 
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (profiles/proj_par_550x128x256_hbm_traffic.md), scaled by the same
-# counters read over a device copy of known size.  Valid only for the kernel
-# sources it was taken with: if they have changed, the figure is withheld.
-TRAFFIC = {"kernel": "proj::k_proj_par", "grid": (550, 128, 256), "source_digest": "91582cb9df19b01c",
-           "bytes_per_launch": 0.5 * ((116247.5 + 126847.7) * 2.0 + 2 * 140800.0) * 1024.0}
+# passes (the profiles/ summary named for that kernel and workload), scaled by
+# the same counters read over a device copy of known size.  Valid only for the
+# kernel sources it was taken with: if they have changed, it is withheld.
+TRAFFIC = {"kernel": "modal::k_modal", "grid": (550, 128, 256), "source_digest": "9c2f4f59636f2b47",
+           "bytes_per_launch": (99297.9 * 2.0 + 156160.0) * 1024.0}
+TRAFFIC_SOURCES = ("modal.hip.h", "modal_layout.h", "radial.hip.h", "solve.hip")
 
 
 def _kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("proj.hip.h", "solve.hip", "proj_layout.h"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_1806_06623_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(parity, nr, nth, nphi):
+def measured_traffic(kernel, nr, nth, nphi):
     t = TRAFFIC
-    if (t is None or not parity or (nr, nth, nphi) != tuple(t["grid"])
+    if (t is None or kernel != t["kernel"] or (nr, nth, nphi) != tuple(t["grid"])
             or _kernel_source_digest() != t["source_digest"]):
         return None
     return round(t["bytes_per_launch"], 0)
@@ -277,11 +288,14 @@ def main():
     log(f"timed {K} solves: {elapsed * 1e3 / K:.3f} ms/solve, {solves_s:.1f} solves/s")
 
     # per-stage durations (HIP events recorded by the library on the solve stream)
+    fused = plan.path == "fused"
     st = np.array([plan.solve_profiled(rho, phi, G=case["G"]) for _ in range(args.profile_steps)])
     stage_ms = st.mean(axis=0)
-    model = stage_model(nr, nth, nphi, plan.parity_split)
+    model = stage_model(nr, nth, nphi, plan.parity_split, fused)
+    # the fused path records the per-mode kernel as stage 1 (stages 2 and 3 are empty)
+    names, times = (FUSED_STAGES, [stage_ms[0], stage_ms[1], stage_ms[4]]) if fused else (STAGES, list(stage_ms))
     stages = {}
-    for name, ms in zip(STAGES, stage_ms):
+    for name, ms in zip(names, times):
         m = model[name]
         d = {"ms": round(float(ms), 5), "alg_bytes": m["bytes"],
              "GBps": round(m["bytes"] / (ms * 1e-3) / 1e9, 1),
@@ -290,30 +304,32 @@ def main():
             d["TFLOPs"] = round(m["flops"] / (ms * 1e-3) / 1e12, 3)
             d["mfma_frac"] = round(m["flops"] / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
         stages[name] = d
-    log("stages: " + ", ".join(f"{k}={v['ms']:.4f}ms" for k, v in stages.items()))
+    log(f"path {plan.path}; stages: " + ", ".join(f"{k}={v['ms']:.4f}ms" for k, v in stages.items()))
 
-    # dominant kernel: the theta projection (two launches per solve).  Its
+    # dominant kernel: the fused per-mode kernel (one launch per solve) or, on
+    # the staged path, the theta projection (two launches per solve).  Its
     # roofline is the larger of the two ideal times: algorithmic bytes at the
-    # HBM peak, algorithmic flops at the FP64 matrix peak.  With the parity
-    # split the flops halve and the bytes bound it.
-    proj_ms = 0.5 * (stage_ms[1] + stage_ms[3])
-    pm = model["projection_forward"]
+    # HBM peak, algorithmic flops at the FP64 matrix peak.
+    if fused:
+        kname, k_ms, pm = "modal::k_modal (fused projection + radial + projection)", stage_ms[1], model["fused_modal"]
+        per = "2 * N_r*N_theta^2*N_phi / 2 (both parity-split products)"
+    else:
+        kname = "proj::k_proj_par (parity split)" if plan.parity_split else "proj::k_proj_f64"
+        k_ms, pm = 0.5 * (stage_ms[1] + stage_ms[3]), model["projection_forward"]
+        per = "N_r*N_theta^2*N_phi, parity split" if plan.parity_split else "2*N_r*N_theta^2*N_phi"
     t_hbm = pm["bytes"] / (HBM_PEAK_GBS * 1e9)
     t_mfma = pm["flops"] / (FP64_PEAK_TFLOPS * 1e12)
-    kname = "proj::k_proj_par (parity split)" if plan.parity_split else "proj::k_proj_f64"
     if t_hbm >= t_mfma:
-        achieved, peak, unit = pm["bytes"] / (proj_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+        achieved, peak, unit = pm["bytes"] / (k_ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
-        achieved, peak, unit = pm["flops"] / (proj_ms * 1e-3) / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        achieved, peak, unit = pm["flops"] / (k_ms * 1e-3) / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
     roofline = {"bound": "hbm" if t_hbm >= t_mfma else "mfma", "kernel": kname,
                 "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": measured_traffic(plan.parity_split, nr, nth, nphi),
-                "per_launch": (f"{pm['bytes']:.4g} algorithmic bytes (rho-spectrum in, projected spectrum out, "
-                               f"one basis per m) and {pm['flops']:.4g} flop "
-                               f"({'N_r*N_theta^2*N_phi, parity split' if plan.parity_split else '2*N_r*N_theta^2*N_phi'}) "
-                               f"per launch; avg launch {proj_ms * 1e3:.1f} us (HIP events on the solve stream); "
-                               f"ideal {t_hbm * 1e6:.1f} us at the HBM peak, {t_mfma * 1e6:.1f} us at the FP64 "
-                               f"matrix peak")}
+                "frac": round(achieved / peak, 4), "traffic": measured_traffic(kname.split(" ")[0], nr, nth, nphi),
+                "per_launch": (f"{pm['bytes']:.4g} algorithmic bytes (spectrum in, result out, eigenvector "
+                               f"matrices) and {pm['flops']:.4g} flop ({per}) per launch; avg launch "
+                               f"{k_ms * 1e3:.1f} us (HIP events on the solve stream); ideal {t_hbm * 1e6:.1f} us at "
+                               f"the HBM peak, {t_mfma * 1e6:.1f} us at the FP64 matrix peak")}
 
     # mixed-precision form on the same workload (FP32-MFMA projections + FP64 refinement)
     mixed = None
@@ -343,7 +359,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded stellar-core density: profile x lognormal field + point mass)",
         "config": {"workload": f"stellar_{nr}x{nth}x{nphi}_fp64", "nr": nr, "nth": nth, "nphi": nphi,
-                   "zones": zones, "precision": "fp64"},
+                   "zones": zones, "precision": "fp64", "path": plan.path},
         "gzones_per_s": round(zones * solves_s / 1e9, 3),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
