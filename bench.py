@@ -230,6 +230,8 @@ def main():
     ap.add_argument("--nr", type=int, default=550)
     ap.add_argument("--nth", type=int, default=128)
     ap.add_argument("--nphi", type=int, default=256)
+    ap.add_argument("--path", choices=["auto", "staged", "fused"], default="auto",
+                    help="kernel path of the FP64 solve (auto: fused where the grid allows it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run torch's device copy of one field (5 times), to calibrate the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -260,6 +262,7 @@ def main():
 
     t0 = time.perf_counter()
     plan = spp.Plan(case["r_if"], case["th_if"], nphi, device="cuda:0")
+    plan.path = args.path
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"setup (host eigensolves + upload) {setup_s:.3f} s")
