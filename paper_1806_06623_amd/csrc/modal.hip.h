@@ -112,6 +112,38 @@ __device__ __forceinline__ void stage_image(double* __restrict__ Bs, const doubl
     }
 }
 
+// Move a double between lanes of a 16-lane row (DPP row shift): with
+// CTRL = 0x110 + n (row_shr) lane i receives lane i - n, with 0x100 + n
+// (row_shl) lane i + n; lanes without a source in their row receive `old`.
+template <int CTRL>
+__device__ __forceinline__ double row_move(double v, double old)
+{
+    const long long vb = __double_as_longlong(v), ob = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp(int(ob), int(vb), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(int(ob >> 32), int(vb >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// One level of parallel cyclic reduction over the 16 lanes of a row, stride
+// HS: row t (a x_{t-1} + b x_t + c x_{t+1} = d in the current stride) is
+// combined with rows t - HS and t + HS; a partner outside the row contributes
+// nothing (its coupling to t is zero by construction, and the select keeps a
+// missing partner's value out).
+template <int HS>
+__device__ __forceinline__ void pcr16_level(double& ra, double& rb, double& rc, double& rd, int t)
+{
+    const double am = row_move<0x110 + HS>(ra, 0.0), bm = row_move<0x110 + HS>(rb, 1.0);
+    const double cm = row_move<0x110 + HS>(rc, 0.0), dm = row_move<0x110 + HS>(rd, 0.0);
+    const double ap = row_move<0x100 + HS>(ra, 0.0), bp = row_move<0x100 + HS>(rb, 1.0);
+    const double cp = row_move<0x100 + HS>(rc, 0.0), dp = row_move<0x100 + HS>(rd, 0.0);
+    const double a = t >= HS ? -ra * radial::recip(bm) : 0.0;
+    const double c = t + HS < 16 ? -rc * radial::recip(bp) : 0.0;
+    rb = rb + a * cm + c * ap;
+    rd = rd + a * dm + c * dp;
+    ra = a * am;
+    rc = c * cp;
+}
+
 template <int RN, int T>
 __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const double* __restrict__ Fimg,
                                                    const double* __restrict__ Iimg, const double* __restrict__ lam,
@@ -124,7 +156,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     constexpr int ROWS = NW * 16 * T;       // row capacity
     constexpr int NCH = T * NC;             // load chunks of the forward product
     constexpr int PS = P * 16;              // one reduced-system field: [P][16]
-    constexpr int RED = 14 * PS;            // own[3], nxt[3], two buffers of red[4]
+    constexpr int RED = 6 * PS;             // own[3], nxt[3]
     constexpr int TRB = NW * 16 * TP;       // one 16 x 32 transpose buffer per wave
     constexpr int UN = RED > TRB ? RED : TRB;
     __shared__ __attribute__((aligned(16))) double Bs[ELEMS];
@@ -209,7 +241,6 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     double* nxt = un + 3 * PS;        // [3][P][16]
     const double oL = t_row[s0].w;            // s0 <-> s0+1
     const double oR = t_row[s0 + CH - 1].w;   // last row of the chunk <-> next separator
-    const int pm = p > 0 ? p - 1 : 0;
     const int pp = p < P - 1 ? p + 1 : P - 1;
 
 #pragma unroll
@@ -278,41 +309,49 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         own[(2 * P + p) * 16 + lr] = D(0) - oL * Yf;
         __syncthreads();
         MODAL_PHASE_FENCE();
-        const bool top = p == 0;
-        double rA = top ? 0.0 : nxt[(0 * P + pm) * 16 + lr];
-        double rB = own[(0 * P + p) * 16 + lr] + (top ? 0.0 : nxt[(1 * P + pm) * 16 + lr]);
-        double rC = own[(1 * P + p) * 16 + lr];
-        double rD = own[(2 * P + p) * 16 + lr] - (top ? 0.0 : nxt[(2 * P + pm) * 16 + lr]);
-        // parallel cyclic reduction: after the level of stride hs every row
-        // couples only to rows 2 hs away.  A row with no partner that far has a
-        // zero coupling on that side, so the clamped partner contributes 0.
-        // Two row buffers alternate, one barrier per level.
+        // The separator rows form a tridiagonal system of P = 48 rows per
+        // column.  Waves 0..3 solve it, one 16-lane row per column (column
+        // 4 w + g of this group), lane t holding partitions 3t .. 3t+2: the
+        // two interior rows of each lane are eliminated locally, leaving one
+        // row per lane, which parallel cyclic reduction over the 16 lanes of
+        // the row (DPP row shifts, no barriers) solves in four levels.
+        static_assert(P == 48, "the reduced solve maps 48 partitions onto 16 lanes x 3");
+        if (w < 4) {
+            const int c = 4 * w + g, t = lr;
+            double qa[3], qb[3], qc[3], qd[3];   // rows 3t .. 3t+2
 #pragma unroll
-        for (int lvl = 0; (1 << lvl) < P; ++lvl) {
-            const int hs = 1 << lvl;
-            double* red = un + 6 * PS + (lvl & 1) * 4 * PS;
-            red[(0 * P + p) * 16 + lr] = rA;
-            red[(1 * P + p) * 16 + lr] = rB;
-            red[(2 * P + p) * 16 + lr] = rC;
-            red[(3 * P + p) * 16 + lr] = rD;
-            __syncthreads();
-            MODAL_PHASE_FENCE();
-            // partner rows, recomputed per level (a copy of p laundered through an
-            // empty asm, so the twelve partner addresses are not all kept live)
-            int pl = p;
-            asm volatile("" : "+v"(pl));
-            const int pa = pl >= hs ? pl - hs : 0;
-            const int pc = pl + hs < P ? pl + hs : P - 1;
-            const double a = -rA * radial::recip(red[(1 * P + pa) * 16 + lr]);
-            const double c = -rC * radial::recip(red[(1 * P + pc) * 16 + lr]);
-            const double nb = rB + a * red[(2 * P + pa) * 16 + lr] + c * red[(0 * P + pc) * 16 + lr];
-            const double nd = rD + a * red[(3 * P + pa) * 16 + lr] + c * red[(3 * P + pc) * 16 + lr];
-            rA = a * red[(0 * P + pa) * 16 + lr];
-            rC = c * red[(2 * P + pc) * 16 + lr];
-            rB = nb;
-            rD = nd;
+            for (int r = 0; r < 3; ++r) {
+                const int pr = 3 * t + r;
+                const int pq = pr > 0 ? pr - 1 : 0;
+                const bool first = pr == 0;
+                qa[r] = first ? 0.0 : nxt[(0 * P + pq) * 16 + c];
+                qb[r] = own[(0 * P + pr) * 16 + c] + (first ? 0.0 : nxt[(1 * P + pq) * 16 + c]);
+                qc[r] = own[(1 * P + pr) * 16 + c];
+                qd[r] = own[(2 * P + pr) * 16 + c] - (first ? 0.0 : nxt[(2 * P + pq) * 16 + c]);
+            }
+            // rows 3t+1, 3t+2 in terms of x_{3t} and x_{3t+3}:
+            //   x_{3t+1} = e1 + f1 x_{3t} + g1 x_{3t+3},  x_{3t+2} = e2 + f2 x_{3t} + g2 x_{3t+3}
+            const double idet = radial::recip(qb[1] * qb[2] - qc[1] * qa[2]);
+            const double e1 = (qb[2] * qd[1] - qc[1] * qd[2]) * idet, f1 = -qb[2] * qa[1] * idet, g1 = qc[1] * qc[2] * idet;
+            const double e2 = (qb[1] * qd[2] - qa[2] * qd[1]) * idet, f2 = qa[2] * qa[1] * idet, g2 = -qb[1] * qc[2] * idet;
+            // the previous lane's x_{3t-1} = e2' + f2' x_{3t-3} + g2' x_{3t} enters row 3t
+            // (lane 0 has qa[0] = 0)
+            const double e2p = row_move<0x111>(e2, 0.0), f2p = row_move<0x111>(f2, 0.0);
+            const double g2p = row_move<0x111>(g2, 0.0);
+            double ra = qa[0] * f2p;
+            double rb = qb[0] + qa[0] * g2p + qc[0] * f1;
+            double rc = qc[0] * g1;
+            double rd = qd[0] - qa[0] * e2p - qc[0] * e1;
+            pcr16_level<1>(ra, rb, rc, rd, t);
+            pcr16_level<2>(ra, rb, rc, rd, t);
+            pcr16_level<4>(ra, rb, rc, rd, t);
+            pcr16_level<8>(ra, rb, rc, rd, t);
+            const double x0 = rd * radial::recip(rb);
+            const double x3 = row_move<0x101>(x0, 0.0);    // x_{3t+3}; lane 15 has g1 = g2 = 0
+            xs[(3 * t + 0) * 16 + c] = x0;
+            xs[(3 * t + 1) * 16 + c] = e1 + f1 * x0 + g1 * x3;
+            xs[(3 * t + 2) * 16 + c] = e2 + f2 * x0 + g2 * x3;
         }
-        xs[p * 16 + lr] = rD * radial::recip(rB);
         __syncthreads();
         MODAL_PHASE_FENCE();
 
@@ -375,7 +414,6 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         for (int cb = 0; cb < RN; ++cb) out[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < NC; ++kc) {
-            MODAL_PHASE_FENCE();
             // columns 32 kc .. 32 kc + 31 of tile rb, row r = g + 4 v
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
