@@ -36,6 +36,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "modal_layout.h"
 #include "radial.hip.h"
 
@@ -112,6 +114,16 @@ __device__ __forceinline__ void stage_image(double* __restrict__ Bs, const doubl
     }
 }
 
+// Calls f(integral_constant<int, I>) for I = I0 .. N-1 in order.
+template <int I0, int N, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I0 < N) {
+        f(std::integral_constant<int, I0>{});
+        static_for<I0 + 1, N>(f);
+    }
+}
+
 // Move a double between lanes of a 16-lane row (DPP row shift): with
 // CTRL = 0x110 + n (row_shr) lane i receives lane i - n, with 0x100 + n
 // (row_shl) lane i + n; lanes without a source in their row receive `old`.
@@ -155,17 +167,18 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     constexpr int CH = 4 * T;               // rows per lane chunk
     constexpr int ROWS = NW * 16 * T;       // row capacity
     constexpr int NCH = T * NC;             // load chunks of the forward product
-    constexpr int PS = P * 16;              // one reduced-system field: [P][16]
-    constexpr int RED = 6 * PS;             // own[3], nxt[3]
+    constexpr int FP = 17;                  // pitch of a partition row in the [P][16] fields (bank skew)
+    constexpr int PS = P * FP;              // one reduced-system field: [P][16] with that pitch
+    constexpr int RED = 12 * PS;            // two buffers of own[3], nxt[3]
     constexpr int TRB = NW * 16 * TP;       // one 16 x 32 transpose buffer per wave
     constexpr int UN = RED > TRB ? RED : TRB;
     __shared__ __attribute__((aligned(16))) double Bs[ELEMS];
     __shared__ __attribute__((aligned(16))) double un[UN];
-    __shared__ double xs[P * 16];
+    __shared__ double xs[2 * PS];           // two buffers of the separator values
     // per-row radial coefficients {-(alpha_{i-1} + alpha_i), V_i R_i, [i = N_r - 1],
     // alpha_i}, so that the diagonal for eigenvalue lambda and outer coefficient
     // beta is x + y lambda - z beta; rows >= N_r are decoupled identity rows
-    __shared__ double4 t_row[ROWS];
+    __shared__ double4 t_row[ROWS + P];     // row i at i + i / CH: one skew slot per chunk
     __shared__ double t_V[ROWS];
     __shared__ double t_lam[16 * RN], t_bo[16 * RN];   // lambda_l, beta_l of this (m, parity)
 
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         const bool in = i < nr;
         const double a = in ? tab.alpha[i] : 0.0;
         const double am = (in && i > 0) ? tab.alpha[i - 1] : 0.0;
-        t_row[i] = double4{in ? -(am + a) : 1.0, in ? tab.VR[i] : 0.0, i == nr - 1 ? 1.0 : 0.0, a};
+        t_row[i + i / CH] = double4{in ? -(am + a) : 1.0, in ? tab.VR[i] : 0.0, i == nr - 1 ? 1.0 : 0.0, a};
         t_V[i] = in ? tab.V[i] : 0.0;
     }
     __syncthreads();
@@ -237,32 +250,35 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             for (int v = 0; v < 4; ++v) sl[rb][cb][v] = acc[rb][cb][v];
 #define D(k) sl[(k) >> 2][cb][(k) & 3]
 
-    double* own = un;                 // [3][P][16]
-    double* nxt = un + 3 * PS;        // [3][P][16]
-    const double oL = t_row[s0].w;            // s0 <-> s0+1
-    const double oR = t_row[s0 + CH - 1].w;   // last row of the chunk <-> next separator
+    const int sk = s0 + p;                    // this chunk's first record in t_row (skewed)
+    const double oL = t_row[sk].w;            // s0 <-> s0+1
+    const double oR = t_row[sk + CH - 1].w;   // last row of the chunk <-> next separator
     const int pp = p < P - 1 ? p + 1 : P - 1;
 
-#pragma unroll
-    for (int cb = 0; cb < RN; ++cb) {
-        MODAL_PHASE_FENCE();
-        const double lm = t_lam[lr + 16 * cb];
-        const double bo = t_bo[lr + 16 * cb];
-#pragma unroll
-        for (int k = 0; k < CH; ++k) D(k) *= t_V[s0 + k];
-        // Row records are read one row ahead: the empty asm statements take the
-        // previous row's pivot as input, which pins the load of row k+1 after
-        // the pivot of row k-1 and the first use of row k after the pivot of
-        // row k-1, so the load latency overlaps one row of the recurrence and
-        // the records of the other rows are never live at the same time.
-        int rb0 = s0;
+    // Row records are read one row ahead: the empty asm statements take the
+    // previous row's pivot as input, which pins the load of row k+1 after the
+    // pivot of row k-1 and the first use of row k after the pivot of row k-1,
+    // so the load latency overlaps one row of the recurrence and the records
+    // of the other rows are never live at the same time.
 #define ROW(k) t_row[rb0 + (k)]
 #define DIAG(r) ((r).x + (r).y * lm - (r).z * bo)
 #define TIE(r, dep) asm volatile("" : "+v"((r).x), "+v"((r).y), "+v"((r).z), "+v"((r).w) : "v"(dep))
 #define NEXT_BASE(dep) asm volatile("" : "+v"(rb0) : "v"(dep))
 
-        // pass 1, forward: pivots of rows 1 .. CH-1; last interior row in terms of
-        // the separators (only the previous pivot is kept)
+    // pass 1 of column group cb: eliminate the interior rows 1 .. CH-1 of the
+    // chunk in both directions and write this partition's separator row and
+    // its contribution to the next separator row (buffer cb % 2)
+    auto pass1 = [&](auto cbc) __attribute__((always_inline)) {
+        constexpr int cb = decltype(cbc)::value;
+        double* own = un + (cb & 1) * 6 * PS;   // [3][P][16]
+        double* nxt = own + 3 * PS;             // [3][P][16]
+        const double lm = t_lam[lr + 16 * cb];
+        const double bo = t_bo[lr + 16 * cb];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) D(k) *= t_V[s0 + k];
+        int rb0 = sk;
+        // forward: last interior row in terms of the separators (the pivots
+        // are recomputed in pass 2 rather than kept)
         double4 cur = ROW(1);
         double4 nx = ROW(2);
         double iw = radial::recip(DIAG(cur));
@@ -279,12 +295,10 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             u = -mult * u;
             al_prev = cur.w;
         }
-        // contribution of this chunk to the next separator row
-        nxt[(0 * P + p) * 16 + lr] = oR * (u * iw);
-        nxt[(1 * P + p) * 16 + lr] = oR * (-oR * iw);
-        nxt[(2 * P + p) * 16 + lr] = oR * (z * iw);
-
-        // pass 1, backward: first interior row in terms of the separators
+        nxt[(0 * P + p) * FP + lr] = oR * (u * iw);
+        nxt[(1 * P + p) * FP + lr] = oR * (-oR * iw);
+        nxt[(2 * P + p) * FP + lr] = oR * (z * iw);
+        // backward: first interior row in terms of the separators
         NEXT_BASE(iw);
         cur = ROW(CH - 1);
         nx = ROW(CH - 2);
@@ -302,71 +316,79 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             vh = -mult * vh;
         }
         const double Yf = zh * iwh, Vf = vh * iwh, Uf = -oL * iwh;
+        own[(0 * P + p) * FP + lr] = DIAG(t_row[sk]) + oL * Uf;
+        own[(1 * P + p) * FP + lr] = oL * Vf;
+        own[(2 * P + p) * FP + lr] = D(0) - oL * Yf;
+    };
 
-        // reduced system over the separators (one row per partition, 16 columns)
-        own[(0 * P + p) * 16 + lr] = DIAG(t_row[s0]) + oL * Uf;
-        own[(1 * P + p) * 16 + lr] = oL * Vf;
-        own[(2 * P + p) * 16 + lr] = D(0) - oL * Yf;
-        __syncthreads();
-        MODAL_PHASE_FENCE();
-        // The separator rows form a tridiagonal system of P = 48 rows per
-        // column.  Waves 0..3 solve it, one 16-lane row per column (column
-        // 4 w + g of this group), lane t holding partitions 3t .. 3t+2: the
-        // two interior rows of each lane are eliminated locally, leaving one
-        // row per lane, which parallel cyclic reduction over the 16 lanes of
-        // the row (DPP row shifts, no barriers) solves in four levels.
-        static_assert(P == 48, "the reduced solve maps 48 partitions onto 16 lanes x 3");
-        if (w < 4) {
-            const int c = 4 * w + g, t = lr;
-            double qa[3], qb[3], qc[3], qd[3];   // rows 3t .. 3t+2
+    // The separator rows of a column form a tridiagonal system of P = 48
+    // rows.  A quartet of waves solves it for the 16 columns of group cb, one
+    // 16-lane row per column (column 4 (w % 4) + g), lane t holding
+    // partitions 3t .. 3t+2: the two interior rows of each lane are
+    // eliminated locally, leaving one row per lane, which parallel cyclic
+    // reduction over the 16 lanes of the row (DPP row shifts, no barriers)
+    // solves in four levels.  The separator values go to xs buffer cb % 2.
+    static_assert(P == 48, "the reduced solve maps 48 partitions onto 16 lanes x 3");
+    auto solve = [&](auto cbc) __attribute__((always_inline)) {
+        constexpr int cb = decltype(cbc)::value;
+        const double* own = un + (cb & 1) * 6 * PS;
+        const double* nxt = own + 3 * PS;
+        double* xsb = xs + (cb & 1) * PS;
+        const int c = 4 * (w & 3) + g, t = lr;
+        double qa[3], qb[3], qc[3], qd[3];   // rows 3t .. 3t+2
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const int pr = 3 * t + r;
-                const int pq = pr > 0 ? pr - 1 : 0;
-                const bool first = pr == 0;
-                qa[r] = first ? 0.0 : nxt[(0 * P + pq) * 16 + c];
-                qb[r] = own[(0 * P + pr) * 16 + c] + (first ? 0.0 : nxt[(1 * P + pq) * 16 + c]);
-                qc[r] = own[(1 * P + pr) * 16 + c];
-                qd[r] = own[(2 * P + pr) * 16 + c] - (first ? 0.0 : nxt[(2 * P + pq) * 16 + c]);
-            }
-            // rows 3t+1, 3t+2 in terms of x_{3t} and x_{3t+3}:
-            //   x_{3t+1} = e1 + f1 x_{3t} + g1 x_{3t+3},  x_{3t+2} = e2 + f2 x_{3t} + g2 x_{3t+3}
-            const double idet = radial::recip(qb[1] * qb[2] - qc[1] * qa[2]);
-            const double e1 = (qb[2] * qd[1] - qc[1] * qd[2]) * idet, f1 = -qb[2] * qa[1] * idet, g1 = qc[1] * qc[2] * idet;
-            const double e2 = (qb[1] * qd[2] - qa[2] * qd[1]) * idet, f2 = qa[2] * qa[1] * idet, g2 = -qb[1] * qc[2] * idet;
-            // the previous lane's x_{3t-1} = e2' + f2' x_{3t-3} + g2' x_{3t} enters row 3t
-            // (lane 0 has qa[0] = 0)
-            const double e2p = row_move<0x111>(e2, 0.0), f2p = row_move<0x111>(f2, 0.0);
-            const double g2p = row_move<0x111>(g2, 0.0);
-            double ra = qa[0] * f2p;
-            double rb = qb[0] + qa[0] * g2p + qc[0] * f1;
-            double rc = qc[0] * g1;
-            double rd = qd[0] - qa[0] * e2p - qc[0] * e1;
-            pcr16_level<1>(ra, rb, rc, rd, t);
-            pcr16_level<2>(ra, rb, rc, rd, t);
-            pcr16_level<4>(ra, rb, rc, rd, t);
-            pcr16_level<8>(ra, rb, rc, rd, t);
-            const double x0 = rd * radial::recip(rb);
-            const double x3 = row_move<0x101>(x0, 0.0);    // x_{3t+3}; lane 15 has g1 = g2 = 0
-            xs[(3 * t + 0) * 16 + c] = x0;
-            xs[(3 * t + 1) * 16 + c] = e1 + f1 * x0 + g1 * x3;
-            xs[(3 * t + 2) * 16 + c] = e2 + f2 * x0 + g2 * x3;
+        for (int r = 0; r < 3; ++r) {
+            const int pr = 3 * t + r;
+            const int pq = pr > 0 ? pr - 1 : 0;
+            const bool first = pr == 0;
+            qa[r] = first ? 0.0 : nxt[(0 * P + pq) * FP + c];
+            qb[r] = own[(0 * P + pr) * FP + c] + (first ? 0.0 : nxt[(1 * P + pq) * FP + c]);
+            qc[r] = own[(1 * P + pr) * FP + c];
+            qd[r] = own[(2 * P + pr) * FP + c] - (first ? 0.0 : nxt[(2 * P + pq) * FP + c]);
         }
-        __syncthreads();
-        MODAL_PHASE_FENCE();
+        // rows 3t+1, 3t+2 in terms of x_{3t} and x_{3t+3}:
+        //   x_{3t+1} = e1 + f1 x_{3t} + g1 x_{3t+3},  x_{3t+2} = e2 + f2 x_{3t} + g2 x_{3t+3}
+        const double idet = radial::recip(qb[1] * qb[2] - qc[1] * qa[2]);
+        const double e1 = (qb[2] * qd[1] - qc[1] * qd[2]) * idet, f1 = -qb[2] * qa[1] * idet, g1 = qc[1] * qc[2] * idet;
+        const double e2 = (qb[1] * qd[2] - qa[2] * qd[1]) * idet, f2 = qa[2] * qa[1] * idet, g2 = -qb[1] * qc[2] * idet;
+        // the previous lane's x_{3t-1} = e2' + f2' x_{3t-3} + g2' x_{3t} enters row 3t
+        // (lane 0 has qa[0] = 0)
+        const double e2p = row_move<0x111>(e2, 0.0), f2p = row_move<0x111>(f2, 0.0);
+        const double g2p = row_move<0x111>(g2, 0.0);
+        double ra = qa[0] * f2p;
+        double rb = qb[0] + qa[0] * g2p + qc[0] * f1;
+        double rc = qc[0] * g1;
+        double rd = qd[0] - qa[0] * e2p - qc[0] * e1;
+        pcr16_level<1>(ra, rb, rc, rd, t);
+        pcr16_level<2>(ra, rb, rc, rd, t);
+        pcr16_level<4>(ra, rb, rc, rd, t);
+        pcr16_level<8>(ra, rb, rc, rd, t);
+        const double x0 = rd * radial::recip(rb);
+        const double x3 = row_move<0x101>(x0, 0.0);    // x_{3t+3}; lane 15 has g1 = g2 = 0
+        xsb[(3 * t + 0) * FP + c] = x0;
+        xsb[(3 * t + 1) * FP + c] = e1 + f1 * x0 + g1 * x3;
+        xsb[(3 * t + 2) * FP + c] = e2 + f2 * x0 + g2 * x3;
+    };
 
-        // pass 2: interior with both separators known (pivots recomputed)
-        const double xL = xs[p * 16 + lr];
-        const double xR = xs[pp * 16 + lr];     // multiplied by oR = 0 for the last partition
+    // pass 2 of column group cb: the interior rows with both separators known
+    // (pivots recomputed)
+    auto pass2 = [&](auto cbc) __attribute__((always_inline)) {
+        constexpr int cb = decltype(cbc)::value;
+        const double* xsb = xs + (cb & 1) * PS;
+        const double lm = t_lam[lr + 16 * cb];
+        const double bo = t_bo[lr + 16 * cb];
+        const double xL = xsb[p * FP + lr];
+        const double xR = xsb[pp * FP + lr];     // multiplied by oR = 0 for the last partition
         D(0) = xL;
         D(1) -= oL * xL;
         D(CH - 1) -= oR * xR;
+        int rb0 = sk;
         double invw[CH];
         NEXT_BASE(xL);
-        cur = ROW(1);
-        nx = ROW(2);
+        double4 cur = ROW(1);
+        double4 nx = ROW(2);
         invw[1] = radial::recip(DIAG(cur));
-        al_prev = cur.w;
+        double al_prev = cur.w;
 #pragma unroll
         for (int k = 2; k < CH; ++k) {
             cur = nx;
@@ -378,7 +400,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             D(k) -= mult * D(k - 1);
             al_prev = cur.w;
         }
-        // back substitution; alpha of row k is al(k), read one row ahead
+        // back substitution; alpha of row k is read one row ahead
         double xn = D(CH - 1) * invw[CH - 1];
         D(CH - 1) = xn;
         NEXT_BASE(xn);
@@ -392,11 +414,29 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             xn = (D(k) - ak * xn) * invw[k];
             D(k) = xn;
         }
+    };
+
+    // Software pipeline over the column groups, one barrier per round: in
+    // round r every wave runs pass 2 of group r-2 and pass 1 of group r while
+    // the quartet (r-1) % 3 first solves the reduced system of group r-1.
+    // Pass 1 of a group and its reduced solve, and the solve and pass 2, are
+    // one barrier apart; the double buffers keep rounds r and r+1 apart.
+    const int quartet = w >> 2;
+    auto round = [&](auto rc) __attribute__((always_inline)) {
+        constexpr int r = decltype(rc)::value;
+        MODAL_PHASE_FENCE();
+        if constexpr (r >= 1 && r <= RN) {
+            if (quartet == (r - 1) % 3) solve(std::integral_constant<int, r - 1>{});
+        }
+        if constexpr (r >= 2) pass2(std::integral_constant<int, r - 2>{});
+        if constexpr (r < RN) pass1(std::integral_constant<int, r>{});
+        if constexpr (r <= RN) __syncthreads();
+    };
+    static_for<0, RN + 2>(round);
 #undef ROW
 #undef DIAG
 #undef TIE
 #undef NEXT_BASE
-    }
 #undef D
 
     // ---- inverse projection, tile by tile through a per-wave transpose
