@@ -33,8 +33,12 @@ namespace {
 // line pairs (i, k), (i, N_theta-1-k), k < h = N_theta/2; it transforms the
 // even fold (sum) and the odd fold (difference) and stores them as lines
 // (i, k) and (i, h+k).
-template <int N, bool FOLD = false>
-__global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
+// PERSIST: a grid of resident workgroups loops over the blocks, keeping the
+// loads of its next block in flight; otherwise one block per workgroup, two
+// workgroups per CU, and the hardware overlaps one block's loads with the
+// other's transform and stores.
+template <int N, bool FOLD = false, bool PERSIST = true>
+__global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
                                                   const c64* __restrict__ tw_g, double scale, int nlines,
                                                   int nblocks, int nth)
 {
@@ -97,7 +101,9 @@ __global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_fwd(const double* __r
             }
         }
         __syncthreads();
-        if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
+        if constexpr (PERSIST) {
+            if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
+        }
         fft_passes<N2, 1, T, S::E>(lds + line * LS, tid, tws);
 
         // split Z into the half spectrum X_m and store halfcomplex planes
@@ -140,14 +146,15 @@ __global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_fwd(const double* __r
             }
         }
         __syncthreads();
+        if constexpr (!PERSIST) break;
     }
 }
 
 // With FOLD the block's lines are the even and odd folds (i, k), (i, h+k)
 // of JB/2 pairs; it stores their sum as line (i, k) and their difference as
 // line (i, N_theta-1-k).
-template <int N, bool FOLD = false>
-__global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
+template <int N, bool FOLD = false, bool PERSIST = true>
+__global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
                                                   const c64* __restrict__ tw_g, int nlines, int nblocks, int nth)
 {
     constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
@@ -216,7 +223,9 @@ __global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_inv(const double* __r
             }
         }
         __syncthreads();
-        if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
+        if constexpr (PERSIST) {
+            if (blk + int(gridDim.x) < nblocks) prefetch(blk + gridDim.x);
+        }
         fft_passes<N2, 1, T, S::E>(lds + line * LS, tid, tws);
 
         // x_{2n} = Re z_n, x_{2n+1} = Im z_n with z = conj(FFT(conj Z))
@@ -248,6 +257,7 @@ __global__ __launch_bounds__(FOLD ? 512 : 256) void k_rfft_inv(const double* __r
             }
         }
         __syncthreads();
+        if constexpr (!PERSIST) break;
     }
 }
 
@@ -568,16 +578,16 @@ void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw,
     const int per = (nblocks + res - 1) / res;
     const int grid = (nblocks + per - 1) / per;
     if (forward) {
-        if (fold)
-            hipLaunchKernelGGL((k_rfft_fwd<N, true>), dim3(grid), dim3(512), 0, s, in, out, tw, scale, nlines,
-                               nblocks, nth);
+        if (fold)   // one block per workgroup (see k_rfft_fwd)
+            hipLaunchKernelGGL((k_rfft_fwd<N, true, false>), dim3(nblocks), dim3(512), 0, s, in, out, tw, scale,
+                               nlines, nblocks, nth);
         else
             hipLaunchKernelGGL((k_rfft_fwd<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
                                nblocks, nth);
     } else {
         if (fold)
-            hipLaunchKernelGGL((k_rfft_inv<N, true>), dim3(grid), dim3(512), 0, s, in, out, tw, nlines, nblocks,
-                               nth);
+            hipLaunchKernelGGL((k_rfft_inv<N, true, false>), dim3(nblocks), dim3(512), 0, s, in, out, tw, nlines,
+                               nblocks, nth);
         else
             hipLaunchKernelGGL((k_rfft_inv<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
                                nth);
