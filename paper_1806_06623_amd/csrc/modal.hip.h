@@ -175,11 +175,17 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     __shared__ __attribute__((aligned(16))) double Bs[ELEMS];
     __shared__ __attribute__((aligned(16))) double un[UN];
     __shared__ double xs[2 * PS];           // two buffers of the separator values
-    // per-row radial coefficients {-(alpha_{i-1} + alpha_i), V_i R_i, [i = N_r - 1],
-    // alpha_i}, so that the diagonal for eigenvalue lambda and outer coefficient
-    // beta is x + y lambda - z beta; rows >= N_r are decoupled identity rows
-    __shared__ double4 t_row[ROWS + P];     // row i at i + i / CH: one skew slot per chunk
-    __shared__ double t_V[ROWS];
+    // per-row radial records {x, y, z, a, a^2, V}: x = -(alpha_{i-1} + alpha_i),
+    // y = V_i R_i, z = [i = N_r - 1], a = alpha_i, so that the diagonal for
+    // eigenvalue lambda and outer coefficient beta is x + y lambda - z beta;
+    // rows >= N_r are decoupled identity rows.  Row i sits at i + i / CH; the
+    // interior rows of chunk p (all but its first) are multiplied by the power
+    // of two 2^-e_p (exact), which keeps the continuants of pass 1 near unit
+    // size, and the free slot after each chunk holds {oL, oR, 2^-e_p, -oL oR
+    // 2^-e_p prod of the chunk's scaled interior couplings}, oL and oR the
+    // chunk's (unscaled) couplings to its own and to the next separator.
+    constexpr int RB = 48;                  // bytes per record
+    __shared__ __attribute__((aligned(16))) double t_rec[(ROWS + P) * (RB / 8)];
     __shared__ double t_lam[16 * RN], t_bo[16 * RN];   // lambda_l, beta_l of this (m, parity)
 
     const int par = blockIdx.x, q = blockIdx.y;
@@ -213,12 +219,31 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         t_lam[l] = lam[size_t(m) * nth + L];
         t_bo[l] = beta[size_t(m) * nth + L];
     }
+    // 2^-e_p from the diagonal without the lambda term of the chunk's middle
+    // row (1 on padding rows)
+    auto chunk_scale = [&](int s0c) {
+        const int mid = s0c + CH / 2;
+        const double x = mid < nr ? tab.alpha[mid - 1] + tab.alpha[mid] : 1.0;
+        return ldexp(1.0, -ilogb(x));
+    };
     for (int i = threadIdx.x; i < ROWS; i += THREADS) {
         const bool in = i < nr;
         const double a = in ? tab.alpha[i] : 0.0;
         const double am = (in && i > 0) ? tab.alpha[i - 1] : 0.0;
-        t_row[i + i / CH] = double4{in ? -(am + a) : 1.0, in ? tab.VR[i] : 0.0, i == nr - 1 ? 1.0 : 0.0, a};
-        t_V[i] = in ? tab.V[i] : 0.0;
+        const double sc = i % CH == 0 ? 1.0 : chunk_scale(i - i % CH);
+        double* r = t_rec + (i + i / CH) * (RB / 8);
+        *reinterpret_cast<double4*>(r) = double4{(in ? -(am + a) : 1.0) * sc, (in ? tab.VR[i] : 0.0) * sc,
+                                                 (i == nr - 1 ? 1.0 : 0.0) * sc, a * sc};
+        *reinterpret_cast<double2*>(r + 4) = double2{(a * sc) * (a * sc), (in ? tab.V[i] : 0.0) * sc};
+    }
+    if (threadIdx.x < P) {
+        const int pc = threadIdx.x, s0c = pc * CH;
+        const double sc = chunk_scale(s0c);
+        const double oLc = s0c < nr ? tab.alpha[s0c] : 0.0;
+        const double oRc = s0c + CH - 1 < nr ? tab.alpha[s0c + CH - 1] : 0.0;
+        double pa = 1.0;
+        for (int k = 1; k < CH - 1; ++k) pa *= (s0c + k < nr ? tab.alpha[s0c + k] : 0.0) * sc;
+        *reinterpret_cast<double4*>(t_rec + (s0c + pc + CH) * (RB / 8)) = double4{oLc, oRc, sc, -oLc * oRc * pa * sc};
     }
     __syncthreads();
 
@@ -250,9 +275,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             for (int v = 0; v < 4; ++v) sl[rb][cb][v] = acc[rb][cb][v];
 #define D(k) sl[(k) >> 2][cb][(k) & 3]
 
-    const int sk = s0 + p;                    // this chunk's first record in t_row (skewed)
-    const double oL = t_row[sk].w;            // s0 <-> s0+1
-    const double oR = t_row[sk + CH - 1].w;   // last row of the chunk <-> next separator
+    const int sk = s0 + p;                    // this chunk's first record (skewed)
     const int pp = p < P - 1 ? p + 1 : P - 1;
 
     // Row records are read one row ahead: the empty asm statements take the
@@ -260,65 +283,96 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     // pivot of row k-1 and the first use of row k after the pivot of row k-1,
     // so the load latency overlaps one row of the recurrence and the records
     // of the other rows are never live at the same time.
-#define ROW(k) t_row[rb0 + (k)]
+    // records addressed by a byte offset, so that every row load is one
+    // immediate offset from the same register
+#define REC_AT(off) (reinterpret_cast<const char*>(t_rec) + (off))
+#define ROW(k) (*reinterpret_cast<const double4*>(REC_AT(rb0 + (k) * RB)))
+#define A2(k) (*reinterpret_cast<const double*>(REC_AT(rb0 + (k) * RB + 32)))
+#define VOL(k) (*reinterpret_cast<const double*>(REC_AT(rb0 + (k) * RB + 40)))
+#define TIE1(v, dep) asm volatile("" : "+v"(v) : "v"(dep))
 #define DIAG(r) ((r).x + (r).y * lm - (r).z * bo)
 #define TIE(r, dep) asm volatile("" : "+v"((r).x), "+v"((r).y), "+v"((r).z), "+v"((r).w) : "v"(dep))
 #define NEXT_BASE(dep) asm volatile("" : "+v"(rb0) : "v"(dep))
 
-    // pass 1 of column group cb: eliminate the interior rows 1 .. CH-1 of the
-    // chunk in both directions and write this partition's separator row and
-    // its contribution to the next separator row (buffer cb % 2)
+    // pass 1 of column group cb.  The interior rows 1..n (n = CH - 1) of the
+    // chunk form a tridiagonal block A (scaled by 2^-e_p) coupled to the
+    // separators on either side.  Its continuants, p_k = det of the leading
+    // k x k block and q_k = det of the trailing block from row k, satisfy
+    //   p_k = d_k p_{k-1} - a_{k-1}^2 p_{k-2},  q_k = d_k q_{k+1} - a_k^2 q_{k+2},
+    // and the entries of A^-1 that pass 1 needs are ratios of them:
+    // (A^-1)_nn = p_{n-1}/p_n, (A^-1)_11 = q_2/q_1, (A^-1)_1n = prod a / p_n.
+    // The first and last entries of A^-1 D are T_1/q_1 and S_n/p_n with
+    //   S_k = p_{k-1} D_k - a_{k-1} S_{k-1},  T_k = q_{k+1} D_k - a_k T_{k+1}
+    // Two multiply-adds per row and recurrence, no division; one reciprocal
+    // per sweep.  The partition's separator row and its contribution to the
+    // next separator row go to buffer cb % 2.
+    // n = CH - 1 is odd, so the sign (-1)^(n+1) of (A^-1)_1n is +1
+    static_assert(CH % 2 == 0, "chunks of an even number of rows");
     auto pass1 = [&](auto cbc) __attribute__((always_inline)) {
         constexpr int cb = decltype(cbc)::value;
         double* own = un + (cb & 1) * 6 * PS;   // [3][P][16]
         double* nxt = own + 3 * PS;             // [3][P][16]
         const double lm = t_lam[lr + 16 * cb];
         const double bo = t_bo[lr + 16 * cb];
+        unsigned rb0 = unsigned(sk) * RB;
 #pragma unroll
-        for (int k = 0; k < CH; ++k) D(k) *= t_V[s0 + k];
-        int rb0 = sk;
-        // forward: last interior row in terms of the separators (the pivots
-        // are recomputed in pass 2 rather than kept)
+        for (int k = 0; k < CH; ++k) D(k) *= VOL(k);
+        // forward: pk = p_{k-1}, pk1 = p_{k-2}, al and a2 the coupling of row k-1
         double4 cur = ROW(1);
         double4 nx = ROW(2);
-        double iw = radial::recip(DIAG(cur));
-        double z = D(1), u = -oL, al_prev = cur.w;
+        double a2 = A2(1), a2n = A2(2);
+        double pk = DIAG(cur), pk1 = 1.0, S = D(1), al = cur.w;
 #pragma unroll
         for (int k = 2; k < CH; ++k) {
             cur = nx;
-            TIE(cur, iw);
-            NEXT_BASE(iw);
-            if (k + 1 < CH) nx = ROW(k + 1);
-            const double mult = al_prev * iw;
-            iw = radial::recip(DIAG(cur) - mult * al_prev);
-            z = D(k) - mult * z;
-            u = -mult * u;
-            al_prev = cur.w;
+            double a2c = a2n;
+            TIE(cur, pk);
+            TIE1(a2c, pk);
+            NEXT_BASE(pk);
+            if (k + 1 < CH) {
+                nx = ROW(k + 1);
+                a2n = A2(k + 1);
+            }
+            S = pk * D(k) - al * S;
+            const double pn = DIAG(cur) * pk - a2 * pk1;
+            pk1 = pk;
+            pk = pn;
+            al = cur.w;
+            a2 = a2c;
         }
-        nxt[(0 * P + p) * FP + lr] = oR * (u * iw);
-        nxt[(1 * P + p) * FP + lr] = oR * (-oR * iw);
-        nxt[(2 * P + p) * FP + lr] = oR * (z * iw);
-        // backward: first interior row in terms of the separators
-        NEXT_BASE(iw);
+        const double ipn = radial::recip(pk);
+        NEXT_BASE(ipn);
+        const double4 pt = ROW(CH);             // oL, oR, 2^-e_p, -oL oR 2^-e_p prod a
+        nxt[(0 * P + p) * FP + lr] = pt.w * ipn;
+        nxt[(1 * P + p) * FP + lr] = -(pt.y * pt.y * pt.z) * pk1 * ipn;
+        nxt[(2 * P + p) * FP + lr] = pt.y * S * ipn;
+        // backward: qk = q_{k+1}, qk1 = q_{k+2}
         cur = ROW(CH - 1);
         nx = ROW(CH - 2);
-        double iwh = radial::recip(DIAG(cur));
-        double zh = D(CH - 1), vh = -oR;
+        a2n = A2(CH - 2);
+        double qk = DIAG(cur), qk1 = 1.0, Tk = D(CH - 1);
 #pragma unroll
         for (int k = CH - 2; k >= 1; --k) {
             cur = nx;
-            TIE(cur, iwh);
-            NEXT_BASE(iwh);
-            if (k > 1) nx = ROW(k - 1);
-            const double mult = cur.w * iwh;
-            iwh = radial::recip(DIAG(cur) - mult * cur.w);
-            zh = D(k) - mult * zh;
-            vh = -mult * vh;
+            double a2c = a2n;
+            TIE(cur, qk);
+            TIE1(a2c, qk);
+            NEXT_BASE(qk);
+            if (k > 1) {
+                nx = ROW(k - 1);
+                a2n = A2(k - 1);
+            }
+            Tk = qk * D(k) - cur.w * Tk;
+            const double qn = DIAG(cur) * qk - a2c * qk1;
+            qk1 = qk;
+            qk = qn;
         }
-        const double Yf = zh * iwh, Vf = vh * iwh, Uf = -oL * iwh;
-        own[(0 * P + p) * FP + lr] = DIAG(t_row[sk]) + oL * Uf;
-        own[(1 * P + p) * FP + lr] = oL * Vf;
-        own[(2 * P + p) * FP + lr] = D(0) - oL * Yf;
+        const double iq1 = radial::recip(qk);
+        NEXT_BASE(iq1);
+        const double4 ps = ROW(CH);             // the partition slot again (not kept live)
+        own[(0 * P + p) * FP + lr] = DIAG(ROW(0)) - (ps.x * ps.x * ps.z) * qk1 * iq1;
+        own[(1 * P + p) * FP + lr] = ps.w * iq1;
+        own[(2 * P + p) * FP + lr] = D(0) - ps.x * Tk * iq1;
     };
 
     // The separator rows of a column form a tridiagonal system of P = 48
@@ -377,40 +431,48 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         const double* xsb = xs + (cb & 1) * PS;
         const double lm = t_lam[lr + 16 * cb];
         const double bo = t_bo[lr + 16 * cb];
+        unsigned rb0 = unsigned(sk) * RB;
+        const double4 pt = ROW(CH);
         const double xL = xsb[p * FP + lr];
         const double xR = xsb[pp * FP + lr];     // multiplied by oR = 0 for the last partition
         D(0) = xL;
-        D(1) -= oL * xL;
-        D(CH - 1) -= oR * xR;
-        int rb0 = sk;
+        D(1) -= (pt.x * pt.z) * xL;
+        D(CH - 1) -= (pt.y * pt.z) * xR;
         double invw[CH];
         NEXT_BASE(xL);
         double4 cur = ROW(1);
         double4 nx = ROW(2);
+        double a2p = A2(1), a2n = A2(2);
         invw[1] = radial::recip(DIAG(cur));
         double al_prev = cur.w;
 #pragma unroll
         for (int k = 2; k < CH; ++k) {
             cur = nx;
+            double a2c = a2n;
             TIE(cur, invw[k - 1]);
+            TIE1(a2c, invw[k - 1]);
             NEXT_BASE(invw[k - 1]);
-            if (k + 1 < CH) nx = ROW(k + 1);
+            if (k + 1 < CH) {
+                nx = ROW(k + 1);
+                a2n = A2(k + 1);
+            }
             const double mult = al_prev * invw[k - 1];
-            invw[k] = radial::recip(DIAG(cur) - mult * al_prev);
+            invw[k] = radial::recip(DIAG(cur) - a2p * invw[k - 1]);
             D(k) -= mult * D(k - 1);
             al_prev = cur.w;
+            a2p = a2c;
         }
         // back substitution; alpha of row k is read one row ahead
         double xn = D(CH - 1) * invw[CH - 1];
         D(CH - 1) = xn;
         NEXT_BASE(xn);
-        double an = t_row[rb0 + CH - 2].w;
+        double an = ROW(CH - 2).w;
 #pragma unroll
         for (int k = CH - 2; k >= 1; --k) {
             double ak = an;
             asm volatile("" : "+v"(ak) : "v"(xn));
             NEXT_BASE(xn);
-            if (k > 1) an = t_row[rb0 + k - 1].w;
+            if (k > 1) an = ROW(k - 1).w;
             xn = (D(k) - ak * xn) * invw[k];
             D(k) = xn;
         }
@@ -433,7 +495,11 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         if constexpr (r <= RN) __syncthreads();
     };
     static_for<0, RN + 2>(round);
+#undef REC_AT
 #undef ROW
+#undef A2
+#undef VOL
+#undef TIE1
 #undef DIAG
 #undef TIE
 #undef NEXT_BASE

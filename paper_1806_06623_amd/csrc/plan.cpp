@@ -101,6 +101,65 @@ Geometry make_geometry(const spp_grid_s& g)
     return G;
 }
 
+
+// The fused kernel's pass 1 works with the continuants of each chunk's
+// interior block (determinants of its leading and trailing principal
+// submatrices, rows scaled by 2^-e_p) instead of normalised pivots; they are
+// the products of the pivots and, unlike the pivots, not of unit size.  This
+// bounds their magnitude for every eigenvalue of the plan: from above by
+// Hadamard's bound (product of absolute row sums of the scaled block), from
+// below by the products of the pivot bounds |w_k| >= a_k (resp. a_{k-1} for
+// the trailing ones), which hold because every row has
+// -d_k >= a_{k-1} + a_k (lambda <= 0, beta >= 0); on the outermost row, where
+// a_k = 0, |w_k| >= beta + V R |lambda| instead.  The chunk geometry and the
+// scale follow the kernel: chunks of CH = 4 ceil(N_r / 192) rows, 2^-e_p from
+// the middle row's alpha_{i-1} + alpha_i.  Keeping every partial product
+// within 2^+-300 leaves the right-hand sides, which the continuants multiply,
+// about 2^700 of range.
+bool modal_continuants_in_range(const std::vector<double>& alpha, const std::vector<double>& VR,
+                                const std::vector<double>& lam, const std::vector<double>& beta, int nr)
+{
+    const int T = (nr + 191) / 192, CH = 4 * T, P = 48;
+    double lmax = 0.0, bmax = 0.0, bmin = HUGE_VAL;
+    for (size_t t = 0; t < lam.size(); ++t) {
+        lmax = std::max(lmax, std::fabs(lam[t]));
+        bmax = std::max(bmax, beta[t]);
+        bmin = std::min(bmin, beta[t] + VR[nr - 1] * std::fabs(lam[t]));
+    }
+    const double LIM = 300.0;
+    for (int p = 0; p < P; ++p) {
+        const int s0 = p * CH, mid = s0 + CH / 2;
+        const double sc = mid < nr ? std::ldexp(1.0, -std::ilogb(alpha[mid - 1] + alpha[mid])) : 1.0;
+        const int n = CH - 1;
+        std::vector<double> up(n + 1), lo_f(n + 1), lo_b(n + 1);
+        for (int k = 1; k <= n; ++k) {
+            const int i = s0 + k;
+            if (i >= nr) {            // padding: identity rows, 2^-e_p on the diagonal
+                up[k] = lo_f[k] = lo_b[k] = std::log2(sc);
+                continue;
+            }
+            const double am = alpha[i - 1], a = alpha[i];
+            const double din = (am + a) + VR[i] * lmax + (i == nr - 1 ? bmax : 0.0);
+            const double rs = din + (k > 1 ? am : 0.0) + (k < n ? a : 0.0);
+            up[k] = std::log2(rs * sc);
+            lo_f[k] = std::log2(std::max(i == nr - 1 ? bmin : a, 1e-300) * sc);
+            lo_b[k] = std::log2(std::max(am, 1e-300) * sc);
+        }
+        double su = 0.0, sf = 0.0, sb = 0.0, bu = 0.0;
+        for (int k = 1; k <= n; ++k) {
+            su += up[k];
+            sf += lo_f[k];
+            if (su > LIM || sf < -LIM) return false;
+        }
+        for (int k = n; k >= 1; --k) {
+            bu += up[k];
+            sb += lo_b[k];
+            if (bu > LIM || sb < -LIM) return false;
+        }
+    }
+    return true;
+}
+
 }  // namespace
 
 extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
@@ -322,7 +381,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         // the interleaved k order of modal_layout.h):
         //   forward  B_p[k = j][n = l] = U_p[j][l] dmu_j / sqrt 2
         //   inverse  B_p[k = l][n = j] = U_p[j][l] / sqrt 2
-        p->fused_ok = symmetric && hh % 2 == 0 && hh <= 64 && nr <= modalimg::NRMAX;
+        p->fused_ok = symmetric && hh % 2 == 0 && hh <= 64 && nr <= modalimg::NRMAX &&
+                      modal_continuants_in_range(p->alpha, p->VR, p->lam, p->beta, nr);
         if (p->fused_ok) {
             const int rn = modalimg::rn_for(hh);
             const size_t ie = modalimg::elems(rn);

@@ -103,3 +103,31 @@ def test_host_eigensystems_match_oracle(nth, nphi, uniform):
         assert np.max(np.abs(A_lib - A_ora)) < 1e-12 * np.max(np.abs(lo))
     lib.spp_plan_destroy(p)
     lib.spp_grid_destroy(g)
+
+
+def _host_path(r_if, th_if, nphi):
+    st, g = make_grid(r_if, th_if, nphi)
+    _check(st, "grid")
+    p = _vp()
+    _check(lib.spp_plan_create(g, ctypes.byref(p)), "plan")
+    v = ctypes.c_int()
+    _check(lib.spp_plan_get_path(p, ctypes.byref(v)), "path")
+    lib.spp_plan_destroy(p)
+    lib.spp_grid_destroy(g)
+    return v.value
+
+
+def test_fused_path_range_guard():
+    """The fused kernel eliminates each chunk's interior through continuants
+    (products of pivots), which the plan bounds for every eigenvalue before it
+    selects that kernel.  The stellar radial grid with a uniform theta grid is
+    well inside the range.  Polar theta cells of 1e-6 rad make the largest
+    angular eigenvalue about 1.7e15, and the Hadamard bound of one 12-row
+    chunk's continuants about 2^490, beyond the 2^300 the plan allows: it
+    falls back to the staged kernels."""
+    FUSED, STAGED = 2, 1
+    r_if = synthetic.stellar_r_interfaces(400)
+    assert _host_path(r_if, synthetic.theta_interfaces(16), 64) == FUSED
+    eps = 1e-6
+    th = np.concatenate(([0.0, eps], np.linspace(eps, np.pi - eps, 15)[1:-1], [np.pi - eps, np.pi]))
+    assert _host_path(r_if, th, 64) == STAGED

@@ -97,6 +97,26 @@ def test_fused_white_noise_on_random_widths():
     assert d <= TOL_FP64
 
 
+def test_fused_extreme_radial_widths():
+    """Shells ten times wider than their inner radius (r = 0, 1, 10, ..., 1e39)
+    with a 128-cell theta grid: radial coefficients spanning 80 orders of
+    magnitude, angular eigenvalues up to 2.8e6, and outer-boundary
+    coefficients beta(lambda) that underflow to zero for the largest ones.
+    The fused path's continuants stay in range here (the plan selects it);
+    the source is the stellar profile on this grid."""
+    nr, nth, nphi = 40, 128, 64
+    r_if = np.concatenate(([0.0], 10.0 ** np.arange(0, nr, dtype=np.float64)))
+    th_if = synthetic.theta_interfaces(nth)
+    rho = synthetic.stellar_density(r_if, th_if, nphi, 21, r0=1e20)
+    fused, staged = _both_paths(r_if, th_if, nphi, rho)
+    ref = spectral.solve(r_if, th_if, nphi, rho)
+    e, d = _err(fused, ref), _err(fused, staged)
+    print(f"[parity] extreme widths {nr}x{nth}x{nphi}: vs oracle {e:.3e}, vs staged {d:.3e}", flush=True)
+    assert np.all(np.isfinite(fused))
+    assert e <= TOL_FP64
+    assert d <= TOL_FP64
+
+
 def test_path_selection_rules():
     import paper_1806_06623_amd as spp
     rng, r_if, th_if = _grid(16, 16, 1)
