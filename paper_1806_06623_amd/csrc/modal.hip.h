@@ -96,7 +96,7 @@ __device__ __forceinline__ void mma_chunk(d4 (&acc)[RN], const double (&a)[8], c
 
 // Contiguous copy of one image into LDS (the plan stores it in LDS layout).
 template <int ELEMS>
-__device__ __forceinline__ void stage_image(double* __restrict__ Bs, const double* __restrict__ img)
+__device__ __forceinline__ void stage_image(double* __restrict__ Bs, const double* __restrict__ img, int tid)
 {
     const double2* src = reinterpret_cast<const double2*>(img);
     double2* dst = reinterpret_cast<double2*>(Bs);
@@ -104,12 +104,12 @@ __device__ __forceinline__ void stage_image(double* __restrict__ Bs, const doubl
     double2 v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int i = threadIdx.x + u * THREADS;
+        const int i = tid + u * THREADS;
         v[u] = src[i < HALF ? i : HALF - 1];
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int i = threadIdx.x + u * THREADS;
+        const int i = tid + u * THREADS;
         if (i < HALF) dst[i] = v[u];
     }
 }
@@ -122,6 +122,18 @@ __device__ __forceinline__ void static_for(F&& f)
         f(std::integral_constant<int, I0>{});
         static_for<I0 + 1, N>(f);
     }
+}
+
+// The lane index within the wave, computed afresh from the hardware lane
+// counter; the opaque asm keeps the compiler from reusing an earlier copy.
+// The kernel recomputes lane-derived indices at the start of every phase:
+// values derived once would stay live through the register-heavy radial
+// phase, be spilled, and their reloads would sit on its critical path.
+__device__ __forceinline__ int lane_now()
+{
+    int l = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    asm volatile("" : "+v"(l));
+    return l;
 }
 
 // Move a double between lanes of a 16-lane row (DPP row shift): with
@@ -191,8 +203,8 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     const int par = blockIdx.x, q = blockIdx.y;
     const int m = q <= nphi / 2 ? q : nphi - q;
     const int nr = tab.nr, h = nth >> 1;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int lr = lane & 15, g = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)
+    const int lane = lane_now(), lr = lane & 15, g = lane >> 4;       // forward phase only
     double* __restrict__ Xq = X + size_t(q) * nr * nth + par * h;
 
     // rows supplied as A operand by this lane in tile rb (clamped into range)
@@ -211,7 +223,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     load_a(ba, arow(0), 0, g, h);
     if constexpr (NCH > 1) load_a(bb, arow(1 / NC), 1 % NC, g, h);
 
-    stage_image<ELEMS>(Bs, Fimg + (size_t(m) * 2 + par) * ELEMS);
+    stage_image<ELEMS>(Bs, Fimg + (size_t(m) * 2 + par) * ELEMS, w * 64 + lane);
     // row i: diagonal without the lambda term -(alpha_{i-1} + alpha_i), V_i R_i,
     // coupling alpha_i to row i+1 (alpha_{N_r-1} = 0), V_i
     if (threadIdx.x < 16 * RN) {
@@ -263,8 +275,6 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     // ---- radial solves (partition method on the accumulators, no branches:
     // padding rows have diagonal 1, no coupling and a zero right-hand side,
     // and partitions past the last row reduce to identity rows)
-    const int p = 4 * w + g;                 // partition of this lane group
-    const int s0 = p * CH;                   // its rows s0 .. s0 + CH - 1
     // the slab as scalars from here on (no MFMA register tuples to maintain)
     double sl[T][RN][4];
 #pragma unroll
@@ -275,8 +285,12 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             for (int v = 0; v < 4; ++v) sl[rb][cb][v] = acc[rb][cb][v];
 #define D(k) sl[(k) >> 2][cb][(k) & 3]
 
-    const int sk = s0 + p;                    // this chunk's first record (skewed)
-    const int pp = p < P - 1 ? p + 1 : P - 1;
+    // partition p = 4 w + g of this lane group: rows s0 .. s0 + CH - 1, first
+    // record (skewed) at sk
+#define PART_INDICES()                                                  \
+    const int ln_ = lane_now(), lr = ln_ & 15, p = 4 * w + (ln_ >> 4); \
+    const int s0 = p * CH, sk = s0 + p;                                 \
+    (void)s0; (void)sk
 
     // Row records are read one row ahead: the empty asm statements take the
     // previous row's pivot as input, which pins the load of row k+1 after the
@@ -310,6 +324,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     static_assert(CH % 2 == 0, "chunks of an even number of rows");
     auto pass1 = [&](auto cbc) __attribute__((always_inline)) {
         constexpr int cb = decltype(cbc)::value;
+        PART_INDICES();
         double* own = un + (cb & 1) * 6 * PS;   // [3][P][16]
         double* nxt = own + 3 * PS;             // [3][P][16]
         const double lm = t_lam[lr + 16 * cb];
@@ -388,7 +403,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         const double* own = un + (cb & 1) * 6 * PS;
         const double* nxt = own + 3 * PS;
         double* xsb = xs + (cb & 1) * PS;
-        const int c = 4 * (w & 3) + g, t = lr;
+        const int ln_ = lane_now(), t = ln_ & 15, c = 4 * (w & 3) + (ln_ >> 4);
         double qa[3], qb[3], qc[3], qd[3];   // rows 3t .. 3t+2
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -429,6 +444,8 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     auto pass2 = [&](auto cbc) __attribute__((always_inline)) {
         constexpr int cb = decltype(cbc)::value;
         const double* xsb = xs + (cb & 1) * PS;
+        PART_INDICES();
+        const int pp = p < P - 1 ? p + 1 : P - 1;
         const double lm = t_lam[lr + 16 * cb];
         const double bo = t_bo[lr + 16 * cb];
         unsigned rb0 = unsigned(sk) * RB;
@@ -495,6 +512,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         if constexpr (r <= RN) __syncthreads();
     };
     static_for<0, RN + 2>(round);
+#undef PART_INDICES
 #undef REC_AT
 #undef ROW
 #undef A2
@@ -509,10 +527,14 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     // buffer (wave-local ordering only: LDS operations of one wave complete
     // in order, and the fences keep the compiler from reordering them)
     MODAL_PHASE_FENCE();
-    stage_image<ELEMS>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS);
+    {
+        const int ln_ = lane_now();
+        stage_image<ELEMS>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS, w * 64 + ln_);
+    }
     __syncthreads();
     MODAL_PHASE_FENCE();
     double* tb = un + w * 16 * TP;
+    const int lni = lane_now(), lri = lni & 15, gi = lni >> 4;   // inverse phase
 #pragma unroll
     for (int rb = 0; rb < T; ++rb) {
         d4 out[RN];
@@ -520,13 +542,13 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         for (int cb = 0; cb < RN; ++cb) out[cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < NC; ++kc) {
-            // columns 32 kc .. 32 kc + 31 of tile rb, row r = g + 4 v
+            // columns 32 kc .. 32 kc + 31 of tile rb, row r = gi + 4 v
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int cb = 2 * kc + half;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    tb[(g + 4 * v) * TP + lr + 16 * half] = cb < RN ? sl[rb][cb < RN ? cb : 0][v] : 0.0;
+                    tb[(gi + 4 * v) * TP + lri + 16 * half] = cb < RN ? sl[rb][cb < RN ? cb : 0][v] : 0.0;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -534,21 +556,21 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             double a[8];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const double2 x = *reinterpret_cast<const double2*>(tb + lr * TP + 8 * t + 2 * g);
+                const double2 x = *reinterpret_cast<const double2*>(tb + lri * TP + 8 * t + 2 * gi);
                 a[2 * t] = x.x;
                 a[2 * t + 1] = x.y;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            mma_chunk<RN>(out, a, Bs, kc, g, lr);
+            mma_chunk<RN>(out, a, Bs, kc, gi, lri);
         }
 #pragma unroll
         for (int cb = 0; cb < RN; ++cb) {
-            const int j = lr + 16 * cb;
+            const int j = lri + 16 * cb;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int R = w * 16 * T + g * CH + 4 * rb + v;
+                const int R = w * 16 * T + gi * CH + 4 * rb + v;
                 if (R < nr && j < h) Xq[size_t(R) * nth + j] = out[cb][v];
             }
         }
