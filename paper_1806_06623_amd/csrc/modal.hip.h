@@ -136,6 +136,14 @@ __device__ __forceinline__ int lane_now()
     return l;
 }
 
+// Issue priority of this wave among the waves of its SIMD (0..3).
+template <int PRIO>
+__device__ __forceinline__ void set_priority()
+{
+    static_assert(PRIO >= 0 && PRIO <= 3, "wave priority 0..3");
+    __builtin_amdgcn_s_setprio(PRIO);
+}
+
 // Move a double between lanes of a 16-lane row (DPP row shift): with
 // CTRL = 0x110 + n (row_shr) lane i receives lane i - n, with 0x100 + n
 // (row_shl) lane i + n; lanes without a source in their row receive `old`.
@@ -259,18 +267,23 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     }
     __syncthreads();
 
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int rb = c / NC, kc = c % NC;
-        if (c % 2 == 0) {
+    static_for<0, NCH>([&](auto cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(cc)::value, rb = c / NC, kc = c % NC;
+        // issue priority falls as a wave gets ahead, so that the three waves of
+        // a SIMD share the matrix pipe evenly and finish the product together
+        // (with equal priorities the oldest wave runs ahead and the radial
+        // phase waits for the last one)
+        set_priority<(NCH - 1 - c > 3 ? 3 : NCH - 1 - c)>();
+        if constexpr (c % 2 == 0) {
             mma_chunk<RN>(acc[rb], ba, Bs, kc, g, lr);
-            if (c + 2 < NCH) load_a(ba, arow((c + 2) / NC), (c + 2) % NC, g, h);
+            if constexpr (c + 2 < NCH) load_a(ba, arow((c + 2) / NC), (c + 2) % NC, g, h);
         } else {
             mma_chunk<RN>(acc[rb], bb, Bs, kc, g, lr);
-            if (c + 2 < NCH) load_a(bb, arow((c + 2) / NC), (c + 2) % NC, g, h);
+            if constexpr (c + 2 < NCH) load_a(bb, arow((c + 2) / NC), (c + 2) % NC, g, h);
         }
-    }
+    });
 
+    set_priority<0>();
     MODAL_PHASE_FENCE();
     // ---- radial solves (partition method on the accumulators, no branches:
     // padding rows have diagonal 1, no coupling and a zero right-hand side,
