@@ -25,11 +25,15 @@
 //   w 16 T + (lr % 4) CH + 4 rb + lr / 4), so every lane group owns CH
 //   consecutive rows of each of its columns: a chunk of the radial
 //   partition method, which runs on the accumulators without moving them.
-//   The CH x 4 chunks of the 4 NW lane groups of a column are its
-//   partitions; the reduced (Schur complement) system over their separator
-//   rows is solved by parallel cyclic reduction in LDS, 16 columns at a time.
-//   For the inverse projection each tile is transposed through a small LDS
-//   buffer into the A-operand layout.
+//   The CH-row chunks of the 4 NW lane groups of a column are its
+//   partitions.  Pass 1 eliminates each chunk's interior (through the
+//   continuants of the interior block); the reduced (Schur complement)
+//   system over the 48 separator rows of a column is solved inside one
+//   16-lane row of a wave (local elimination, then cyclic reduction through
+//   DPP row shifts), 16 columns per quartet of waves; pass 2 back-substitutes
+//   the interiors.  The three steps are software-pipelined over the column
+//   groups of 16.  For the inverse projection each tile is transposed
+//   through a small per-wave LDS buffer into the A-operand layout.
 //
 // v_mfma_f64_16x16x4f64 operand layout: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; result register v of lane l is C[l / 16 + 4 v][l % 16].
