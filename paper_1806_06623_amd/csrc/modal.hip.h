@@ -140,6 +140,33 @@ __device__ __forceinline__ int lane_now()
     return l;
 }
 
+// The (component q, parity) unit of workgroup L of the 1-D grid of 2 N_phi.
+// Workgroups are dispatched to the 8 XCDs in turn (L % 8), so units placed
+// at L and L + 8 share an XCD's L2 and start together.  The cosine and sine
+// components of one m (q and N_phi - q) with the same parity read the same
+// eigenvector images; they are paired that way: in each block of 16
+// workgroups, pair k = 8 (L / 16) + L % 8 has its q at L and its N_phi - q at
+// L + 8.  Pairs k < N_phi - 2 are (m = k/2 + 1, parity k % 2); the last two
+// hold the unpaired components q = 0 and q = N_phi/2 (one parity each at L
+// and L + 8).  Grids with N_phi < 8 keep the plain order.
+__device__ __forceinline__ void unit_of(int L, int nphi, int& q, int& par)
+{
+    if (nphi < 8) {
+        par = L & 1;
+        q = L >> 1;
+        return;
+    }
+    const int k = 8 * (L >> 4) + (L & 7), mem = (L >> 3) & 1;
+    if (k < nphi - 2) {
+        const int pm = k >> 1;
+        par = k & 1;
+        q = mem ? nphi - 1 - pm : pm + 1;
+    } else {
+        q = k == nphi - 2 ? 0 : nphi / 2;
+        par = mem;
+    }
+}
+
 // Issue priority of this wave among the waves of its SIMD (0..3).
 template <int PRIO>
 __device__ __forceinline__ void set_priority()
@@ -212,7 +239,8 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     __shared__ __attribute__((aligned(16))) double t_rec[(ROWS + P) * (RB / 8)];
     __shared__ double t_lam[16 * RN], t_bo[16 * RN];   // lambda_l, beta_l of this (m, parity)
 
-    const int par = blockIdx.x, q = blockIdx.y;
+    int q, par;
+    unit_of(blockIdx.x, nphi, q, par);
     const int m = q <= nphi / 2 ? q : nphi - q;
     const int nr = tab.nr, h = nth >> 1;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)

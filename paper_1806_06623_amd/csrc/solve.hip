@@ -525,7 +525,7 @@ bool launch_modal(double* X, const double* Fimg, const double* Iimg, const doubl
     const int rn = modalimg::rn_for(h);
     const int T = (nr + 16 * modal::NW - 1) / (16 * modal::NW);
     if (h % 2 != 0 || h > 64 || T < 1 || T > modalimg::TMAX) return false;
-    const dim3 grid(2, nphi), block(modal::THREADS);
+    const dim3 grid(2 * nphi), block(modal::THREADS);   // one workgroup per (q, parity), see modal::unit_of
 #define SPP_MODAL(RN, TT)                                                                                      \
     case RN * 4 + TT:                                                                                          \
         hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, lam, beta, cf, nth, nphi); \
