@@ -68,8 +68,8 @@ def stage_model(nr, nth, nphi, parity, fused):
 # passes (the profiles/ summary named for that kernel and workload), scaled by
 # the same counters read over a device copy of known size.  Valid only for the
 # kernel sources it was taken with: if they have changed, it is withheld.
-TRAFFIC = {"kernel": "modal::k_modal", "grid": (550, 128, 256), "source_digest": "4b656cbea85352fb",
-           "bytes_per_launch": (91617.3 * 2.0 + 140800.0) * 1024.0}
+TRAFFIC = {"kernel": "modal::k_modal", "grid": (550, 128, 256), "source_digest": "6e768949d06d31e5",
+           "bytes_per_launch": (81325.2 * 2.0 + 140800.0) * 1024.0}
 TRAFFIC_SOURCES = ("modal.hip.h", "modal_layout.h", "radial.hip.h", "solve.hip")
 
 
@@ -233,8 +233,8 @@ def main():
     ap.add_argument("--path", choices=["auto", "staged", "fused"], default="auto",
                     help="kernel path of the FP64 solve (auto: fused where the grid allows it)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run torch's device copy of one field (5 times), to calibrate the "
-                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
+                    help="only run torch's device copy of one field from 5 distinct sources, to "
+                         "calibrate the FETCH_SIZE / WRITE_SIZE counters against a known byte count")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this solver is built and timed on a single MI355X "
@@ -243,10 +243,15 @@ def main():
 
     import torch
     if args.copy_calibration:
+        # five distinct sources, all filled before the first copy: 720 MB written
+        # after any source is filled, so that each copy reads its source from
+        # memory rather than from the 256 MB last-level cache (as the solve's
+        # kernels read their inputs)
         n = args.nr * args.nth * args.nphi
-        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(5):
+        srcs = [torch.full((n,), float(i + 1), dtype=torch.float64, device="cuda:0") for i in range(5)]
+        b = torch.empty_like(srcs[0])
+        torch.cuda.synchronize()
+        for a in srcs:
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read_per_copy": 8 * n, "bytes_written_per_copy": 8 * n,
