@@ -118,6 +118,37 @@ __device__ __forceinline__ void stage_image(double* __restrict__ Bs, const doubl
     }
 }
 
+// Part of an image (COUNT doubles from FIRST) held in registers between its
+// load and its copy into LDS.
+template <int COUNT> struct ImagePart {
+    static constexpr int HALF = COUNT / 2, PER = (HALF + THREADS - 1) / THREADS;
+    double2 v[PER];
+};
+
+template <int FIRST, int COUNT>
+__device__ __forceinline__ void load_part(ImagePart<COUNT>& part, const double* __restrict__ img, int tid)
+{
+    using IP = ImagePart<COUNT>;
+    const double2* src = reinterpret_cast<const double2*>(img + FIRST);
+#pragma unroll
+    for (int u = 0; u < IP::PER; ++u) {
+        const int i = tid + u * THREADS;
+        part.v[u] = src[i < IP::HALF ? i : IP::HALF - 1];
+    }
+}
+
+template <int FIRST, int COUNT>
+__device__ __forceinline__ void store_part(double* __restrict__ Bs, const ImagePart<COUNT>& part, int tid)
+{
+    using IP = ImagePart<COUNT>;
+    double2* dst = reinterpret_cast<double2*>(Bs + FIRST);
+#pragma unroll
+    for (int u = 0; u < IP::PER; ++u) {
+        const int i = tid + u * THREADS;
+        if (i < IP::HALF) dst[i] = part.v[u];
+    }
+}
+
 // Calls f(integral_constant<int, I>) for I = I0 .. N-1 in order.
 template <int I0, int N, class F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -253,7 +284,16 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         return Xq + size_t(R < nr ? R : nr - 1) * nth;
     };
 
-    // ---- forward projection: first two chunks in flight during the staging
+    // ---- forward projection, in chunks c of 8 MFMA steps: column block
+    // kc = c / T (k in [32 kc, 32 kc + 32)) of row tile rb = c % T.  With two
+    // column blocks (SPLIT) the first T chunks use only the image rows of
+    // k < 32, the first half of the image: only that half and chunk 0 are
+    // loaded before the first barrier, so that the first products start on
+    // less data; chunk 1 and the second half follow while they run.
+    constexpr bool SPLIT = NC == 2;
+    constexpr int HALF_E = ELEMS / 2;
+    const double* fimg = Fimg + (size_t(m) * 2 + par) * ELEMS;
+    const int tid0 = w * 64 + lane;
     d4 acc[T][RN];
 #pragma unroll
     for (int rb = 0; rb < T; ++rb)
@@ -261,9 +301,13 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         for (int cb = 0; cb < RN; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
     double ba[8], bb[8];
     load_a(ba, arow(0), 0, g, h);
-    if constexpr (NCH > 1) load_a(bb, arow(1 / NC), 1 % NC, g, h);
-
-    stage_image<ELEMS>(Bs, Fimg + (size_t(m) * 2 + par) * ELEMS, w * 64 + lane);
+    if constexpr (SPLIT) {
+        ImagePart<HALF_E> first;
+        load_part<0, HALF_E>(first, fimg, tid0);
+        store_part<0, HALF_E>(Bs, first, tid0);
+    } else {
+        stage_image<ELEMS>(Bs, fimg, tid0);
+    }
     // row i: diagonal without the lambda term -(alpha_{i-1} + alpha_i), V_i R_i,
     // coupling alpha_i to row i+1 (alpha_{N_r-1} = 0), V_i
     if (threadIdx.x < 16 * RN) {
@@ -298,9 +342,16 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         *reinterpret_cast<double4*>(t_rec + (s0c + pc + CH) * (RB / 8)) = double4{oLc, oRc, sc, -oLc * oRc * pa * sc};
     }
     __syncthreads();
+    if constexpr (NCH > 1) load_a(bb, arow(1 % T), 1 / T, g, h);
+    ImagePart<HALF_E> second;
+    if constexpr (SPLIT) load_part<HALF_E, HALF_E>(second, fimg, tid0);
 
     static_for<0, NCH>([&](auto cc) __attribute__((always_inline)) {
-        constexpr int c = decltype(cc)::value, rb = c / NC, kc = c % NC;
+        constexpr int c = decltype(cc)::value, rb = c % T, kc = c / T;
+        if constexpr (SPLIT && c == T) {
+            store_part<HALF_E, HALF_E>(Bs, second, tid0);
+            __syncthreads();
+        }
         // issue priority falls as a wave gets ahead, so that the three waves of
         // a SIMD share the matrix pipe evenly and finish the product together
         // (with equal priorities the oldest wave runs ahead and the radial
@@ -308,10 +359,10 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         set_priority<(NCH - 1 - c > 3 ? 3 : NCH - 1 - c)>();
         if constexpr (c % 2 == 0) {
             mma_chunk<RN>(acc[rb], ba, Bs, kc, g, lr);
-            if constexpr (c + 2 < NCH) load_a(ba, arow((c + 2) / NC), (c + 2) % NC, g, h);
+            if constexpr (c + 2 < NCH) load_a(ba, arow((c + 2) % T), (c + 2) / T, g, h);
         } else {
             mma_chunk<RN>(acc[rb], bb, Bs, kc, g, lr);
-            if constexpr (c + 2 < NCH) load_a(bb, arow((c + 2) / NC), (c + 2) % NC, g, h);
+            if constexpr (c + 2 < NCH) load_a(bb, arow((c + 2) % T), (c + 2) / T, g, h);
         }
     });
 

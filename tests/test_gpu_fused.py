@@ -64,6 +64,7 @@ def _both_paths(r_if, th_if, nphi, rho):
     (384, 100, 16, 15),   # two full tiles, h = 50 (padded columns)
     (385, 128, 8, 16),    # three tiles, h = 64
     (576, 128, 32, 17),   # largest N_r of the fused kernel
+    (40, 16, 1024, 18),   # 2048 workgroups: the paired unit order far past one round
 ])
 def test_fused_matches_oracle_and_staged(nr, nth, nphi, seed):
     print(f"[case] fused {nr}x{nth}x{nphi} seed {seed}", flush=True)
