@@ -149,6 +149,25 @@ __device__ __forceinline__ void store_part(double* __restrict__ Bs, const ImageP
     }
 }
 
+// Asynchronous copy of an image into LDS without registers (gfx950 LDS DMA)
+// by the NWAVES waves wq = 0 .. NWAVES-1: each copies 1 KB pieces, lane i
+// moving 16 bytes from piece + 16 i to the same offset of the LDS
+// destination.  Completion is awaited with s_waitcnt vmcnt(0) by every wave
+// before a barrier (the compiler also waits before the wave's next LDS read).
+template <int ELEMS, int NWAVES>
+__device__ __forceinline__ void image_dma(double* __restrict__ Bs, const double* __restrict__ img, int wq, int lane)
+{
+    constexpr int PIECES = ELEMS / 128;                 // 128 doubles = 1 KB per wave and piece
+    static_assert(ELEMS % 128 == 0, "image in whole 1 KB pieces");
+#pragma unroll
+    for (int u = 0; u < (PIECES + NWAVES - 1) / NWAVES; ++u) {
+        const int pc = wq + NWAVES * u;                 // wave-uniform
+        if (pc < PIECES)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(img + pc * 128 + 2 * lane),
+                                             (__attribute__((address_space(3))) void*)(Bs + pc * 128), 16, 0, 0);
+    }
+}
+
 // Calls f(integral_constant<int, I>) for I = I0 .. N-1 in order.
 template <int I0, int N, class F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -605,6 +624,14 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         }
         if constexpr (r >= 2) pass2(std::integral_constant<int, r - 2>{});
         if constexpr (r < RN) pass1(std::integral_constant<int, r>{});
+        // the inverse image goes into the forward image's LDS (free since the
+        // end of round 0) by direct copies from quartet 2, issued at the end of
+        // round 2: the barrier waits for their completion, but in round 2
+        // quartet 2 would wait there for the solving quartet 1 anyway; the
+        // inverse phase then starts without a load
+        if constexpr (r == 2 && RN >= 2) {
+            if (quartet == 2) image_dma<ELEMS, 4>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS, w - 8, lane_now());
+        }
         if constexpr (r <= RN) __syncthreads();
     };
     static_for<0, RN + 2>(round);
@@ -623,7 +650,9 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     // buffer (wave-local ordering only: LDS operations of one wave complete
     // in order, and the fences keep the compiler from reordering them)
     MODAL_PHASE_FENCE();
-    {
+    if constexpr (RN >= 2) {
+        __builtin_amdgcn_s_waitcnt(0);     // this wave's image pieces have landed
+    } else {                               // a single column group: no round 1 to hide the copy in
         const int ln_ = lane_now();
         stage_image<ELEMS>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS, w * 64 + ln_);
     }
