@@ -179,14 +179,15 @@ __device__ __forceinline__ void static_for(F&& f)
 }
 
 // The lane index within the wave, computed afresh from the hardware lane
-// counter; the opaque asm keeps the compiler from reusing an earlier copy.
-// The kernel recomputes lane-derived indices at the start of every phase:
-// values derived once would stay live through the register-heavy radial
-// phase, be spilled, and their reloads would sit on its critical path.
+// counter (mbcnt over a full mask) inside an opaque asm, so that the compiler
+// cannot keep one copy and reuse it.  The kernel recomputes lane-derived
+// indices at the start of every phase: values derived once would stay live
+// through the register-heavy phases, be spilled, and their reloads would sit
+// on the critical path.
 __device__ __forceinline__ int lane_now()
 {
-    int l = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-    asm volatile("" : "+v"(l));
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
     return l;
 }
 
