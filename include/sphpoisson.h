@@ -281,7 +281,10 @@ spp_status spp_plan_parity_split(spp_plan p, int* on);
  * Kernel path of the FP64 solves of a plan (spp_solve, spp_solve_profiled,
  * batches and servers created afterwards).  The fused path applies to
  * equator-symmetric theta grids (Sec. 4.2) with N_theta % 4 == 0,
- * N_theta <= 128 and N_r <= 576: the forward FFT stores the even and odd
+ * N_theta <= 128 and N_r <= 576 whose radial systems keep the products of
+ * pivots over the kernel's chunks of rows within 2^+-300 for every
+ * eigenvalue (the plan checks this bound; only extreme grids fail it, e.g.
+ * polar cells of 1e-6 rad): the forward FFT stores the even and odd
  * theta folds s_j +- s_{N-1-j}; one kernel per (Fourier component, parity)
  * then runs the forward projection, the radial solves of Sec. 3.2 and the
  * inverse projection with its N_r x N_theta/2 slab held on chip; the

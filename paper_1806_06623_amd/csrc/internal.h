@@ -33,6 +33,7 @@ struct spp_plan_layout {
     size_t Hpar = 0;
     size_t Fimg = 0;    // fused per-mode kernel images, [M][2][KP][NP] (forward, then inverse)
     size_t Iimg = 0;
+    size_t Rimg = 0;    // radial row records of the fused kernel (modal_layout.h)
     size_t sig = 0;     // theta face coefficients sigma_{j+1/2}, [N_theta + 1] (poles 0)
     size_t dmu = 0;     // cos theta_{j-1/2} - cos theta_{j+1/2}, [N_theta]
     size_t Sj = 0;      // S_j, [N_theta]
@@ -50,7 +51,7 @@ struct spp_plan_s {
     int proj_rn = 0;                           // tile width of the projection kernel (0: fallback)
     bool parity = false;                       // equator-symmetric theta grid: modes ordered even, odd
     int par_rn = 0;                            // tile width of the parity-split kernel (0: not used)
-    std::vector<double> Fimg, Iimg;            // images of the fused per-mode kernel
+    std::vector<double> Fimg, Iimg, Rimg;      // images of the fused per-mode kernel
     bool fused_ok = false;                     // the fused per-mode path can run this grid
     std::atomic<int> path{SPP_PATH_AUTO};      // requested path (spp_plan_set_path)
     spp_plan_layout lay;

@@ -260,7 +260,8 @@ __device__ __forceinline__ void pcr16_level(double& ra, double& rb, double& rc, 
 
 template <int RN, int T>
 __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const double* __restrict__ Fimg,
-                                                   const double* __restrict__ Iimg, const double* __restrict__ lam,
+                                                   const double* __restrict__ Iimg, const double* __restrict__ Rimg,
+                                                   const double* __restrict__ lam,
                                                    const double* __restrict__ beta, radial::Coef tab, int nth,
                                                    int nphi)
 {
@@ -285,8 +286,10 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     // of two 2^-e_p (exact), which keeps the continuants of pass 1 near unit
     // size, and the free slot after each chunk holds {oL, oR, 2^-e_p, -oL oR
     // 2^-e_p prod of the chunk's scaled interior couplings}, oL and oR the
-    // chunk's (unscaled) couplings to its own and to the next separator.
-    constexpr int RB = 48;                  // bytes per record
+    // chunk's (unscaled) couplings to its own and to the next separator.  The
+    // plan builds this image (it depends on the radial grid only).
+    constexpr int RB = 8 * modalimg::RECD;  // bytes per record
+    static_assert(ROWS + P == modalimg::rec_records(T), "record image of the plan");
     __shared__ __attribute__((aligned(16))) double t_rec[(ROWS + P) * (RB / 8)];
     __shared__ double t_lam[16 * RN], t_bo[16 * RN];   // lambda_l, beta_l of this (m, parity)
 
@@ -328,39 +331,14 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     } else {
         stage_image<ELEMS>(Bs, fimg, tid0);
     }
-    // row i: diagonal without the lambda term -(alpha_{i-1} + alpha_i), V_i R_i,
-    // coupling alpha_i to row i+1 (alpha_{N_r-1} = 0), V_i
+    // lambda_l and beta_l of this (m, parity), one per column
     if (threadIdx.x < 16 * RN) {
         const int l = threadIdx.x, L = par * h + (l < h ? l : h - 1);
         t_lam[l] = lam[size_t(m) * nth + L];
         t_bo[l] = beta[size_t(m) * nth + L];
     }
-    // 2^-e_p from the diagonal without the lambda term of the chunk's middle
-    // row (1 on padding rows)
-    auto chunk_scale = [&](int s0c) {
-        const int mid = s0c + CH / 2;
-        const double x = mid < nr ? tab.alpha[mid - 1] + tab.alpha[mid] : 1.0;
-        return ldexp(1.0, -ilogb(x));
-    };
-    for (int i = threadIdx.x; i < ROWS; i += THREADS) {
-        const bool in = i < nr;
-        const double a = in ? tab.alpha[i] : 0.0;
-        const double am = (in && i > 0) ? tab.alpha[i - 1] : 0.0;
-        const double sc = i % CH == 0 ? 1.0 : chunk_scale(i - i % CH);
-        double* r = t_rec + (i + i / CH) * (RB / 8);
-        *reinterpret_cast<double4*>(r) = double4{(in ? -(am + a) : 1.0) * sc, (in ? tab.VR[i] : 0.0) * sc,
-                                                 (i == nr - 1 ? 1.0 : 0.0) * sc, a * sc};
-        *reinterpret_cast<double2*>(r + 4) = double2{(a * sc) * (a * sc), (in ? tab.V[i] : 0.0) * sc};
-    }
-    if (threadIdx.x < P) {
-        const int pc = threadIdx.x, s0c = pc * CH;
-        const double sc = chunk_scale(s0c);
-        const double oLc = s0c < nr ? tab.alpha[s0c] : 0.0;
-        const double oRc = s0c + CH - 1 < nr ? tab.alpha[s0c + CH - 1] : 0.0;
-        double pa = 1.0;
-        for (int k = 1; k < CH - 1; ++k) pa *= (s0c + k < nr ? tab.alpha[s0c + k] : 0.0) * sc;
-        *reinterpret_cast<double4*>(t_rec + (s0c + pc + CH) * (RB / 8)) = double4{oLc, oRc, sc, -oLc * oRc * pa * sc};
-    }
+    // the radial row records (built by the plan, the same for every unit)
+    stage_image<(ROWS + P) * modalimg::RECD>(t_rec, Rimg, tid0);
     __syncthreads();
     if constexpr (NCH > 1) load_a(bb, arow(1 % T), 1 / T, g, h);
     ImagePart<HALF_E> second;

@@ -21,6 +21,16 @@ constexpr int TMAX = 3;                      // row tiles of 16 per wave
 constexpr int NRMAX = NW * 16 * TMAX;        // largest N_r of the fused kernel (576)
 
 constexpr int rn_for(int h) { return h <= 16 ? 1 : h <= 32 ? 2 : 4; }
+
+// Radial row records of the fused kernel, one image per plan (they depend on
+// the radial grid only).  Row tiles per wave T = ceil(N_r / (16 NW)), chunks
+// of CH = 4 T rows, P = 4 NW chunks; row i's record {x, y, z, a, a^2, V}
+// (RECD doubles) sits at record i + i / CH, and the free record after each
+// chunk holds the chunk's {oL, oR, 2^-e_p, -oL oR 2^-e_p prod a}.
+constexpr int RECD = 6;
+constexpr int t_for(int nr) { return (nr + 16 * NW - 1) / (16 * NW); }
+constexpr int rec_records(int T) { return NW * 16 * T + 4 * NW; }
+constexpr size_t rec_elems(int T) { return size_t(rec_records(T)) * RECD; }
 constexpr int kp(int RN) { return RN == 4 ? 64 : 32; }
 constexpr int np(int RN) { return 16 * RN + 16; }
 constexpr size_t elems(int RN) { return size_t(kp(RN)) * np(RN); }

@@ -116,10 +116,19 @@ Geometry make_geometry(const spp_grid_s& g)
 // the middle row's alpha_{i-1} + alpha_i.  Keeping every partial product
 // within 2^+-300 leaves the right-hand sides, which the continuants multiply,
 // about 2^700 of range.
+// Scale 2^-e_p of the chunk of CH rows from s0: the power of two at or below
+// alpha_{mid-1} + alpha_mid of its middle row (the diagonal without the
+// lambda term), 1 for a chunk whose middle row is padding.
+double chunk_scale(const std::vector<double>& alpha, int nr, int s0, int CH)
+{
+    const int mid = s0 + CH / 2;
+    return mid < nr ? std::ldexp(1.0, -std::ilogb(alpha[mid - 1] + alpha[mid])) : 1.0;
+}
+
 bool modal_continuants_in_range(const std::vector<double>& alpha, const std::vector<double>& VR,
                                 const std::vector<double>& lam, const std::vector<double>& beta, int nr)
 {
-    const int T = (nr + 191) / 192, CH = 4 * T, P = 48;
+    const int T = modalimg::t_for(nr), CH = 4 * T, P = 4 * modalimg::NW;
     double lmax = 0.0, bmax = 0.0, bmin = HUGE_VAL;
     for (size_t t = 0; t < lam.size(); ++t) {
         lmax = std::max(lmax, std::fabs(lam[t]));
@@ -128,8 +137,8 @@ bool modal_continuants_in_range(const std::vector<double>& alpha, const std::vec
     }
     const double LIM = 300.0;
     for (int p = 0; p < P; ++p) {
-        const int s0 = p * CH, mid = s0 + CH / 2;
-        const double sc = mid < nr ? std::ldexp(1.0, -std::ilogb(alpha[mid - 1] + alpha[mid])) : 1.0;
+        const int s0 = p * CH;
+        const double sc = chunk_scale(alpha, nr, s0, CH);
         const int n = CH - 1;
         std::vector<double> up(n + 1), lo_f(n + 1), lo_b(n + 1);
         for (int k = 1; k <= n; ++k) {
@@ -158,6 +167,45 @@ bool modal_continuants_in_range(const std::vector<double>& alpha, const std::vec
         }
     }
     return true;
+}
+
+// The record image of modal_layout.h: per row the diagonal without the lambda
+// term x = -(alpha_{i-1} + alpha_i), y = V_i R_i, the outer-row flag z, the
+// coupling a = alpha_i to row i+1, a^2 and V_i (rows >= N_r: identity rows);
+// every chunk's rows but its first (the separator) multiplied by its scale.
+std::vector<double> modal_records(const std::vector<double>& alpha, const std::vector<double>& VR,
+                                  const std::vector<double>& V, int nr)
+{
+    using namespace modalimg;
+    const int T = t_for(nr), CH = 4 * T, ROWS = NW * 16 * T, P = 4 * NW;
+    std::vector<double> rec(rec_elems(T), 0.0);
+    for (int i = 0; i < ROWS; ++i) {
+        const bool in = i < nr;
+        const double a = in ? alpha[i] : 0.0;
+        const double am = (in && i > 0) ? alpha[i - 1] : 0.0;
+        const double sc = i % CH == 0 ? 1.0 : chunk_scale(alpha, nr, i - i % CH, CH);
+        double* r = &rec[size_t(i + i / CH) * RECD];
+        r[0] = (in ? -(am + a) : 1.0) * sc;
+        r[1] = (in ? VR[i] : 0.0) * sc;
+        r[2] = (i == nr - 1 ? 1.0 : 0.0) * sc;
+        r[3] = a * sc;
+        r[4] = (a * sc) * (a * sc);
+        r[5] = (in ? V[i] : 0.0) * sc;
+    }
+    for (int p = 0; p < P; ++p) {
+        const int s0 = p * CH;
+        const double sc = chunk_scale(alpha, nr, s0, CH);
+        const double oL = s0 < nr ? alpha[s0] : 0.0;
+        const double oR = s0 + CH - 1 < nr ? alpha[s0 + CH - 1] : 0.0;
+        double pa = 1.0;
+        for (int k = 1; k < CH - 1; ++k) pa *= (s0 + k < nr ? alpha[s0 + k] : 0.0) * sc;
+        double* r = &rec[size_t(s0 + p + CH) * RECD];
+        r[0] = oL;
+        r[1] = oR;
+        r[2] = sc;
+        r[3] = -oL * oR * pa * sc;
+    }
+    return rec;
 }
 
 }  // namespace
@@ -388,6 +436,7 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             const size_t ie = modalimg::elems(rn);
             const int NP = modalimg::np(rn);
             const double r2 = std::sqrt(0.5);
+            p->Rimg = modal_records(p->alpha, p->VR, p->V, nr);
             p->Fimg.assign(size_t(nm) * 2 * ie, 0.0);
             p->Iimg.assign(size_t(nm) * 2 * ie, 0.0);
             for (int m = 0; m < nm; ++m)
@@ -432,6 +481,7 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.Hpar = take(p->Hpar.size());
         L.Fimg = take(p->Fimg.size());
         L.Iimg = take(p->Iimg.size());
+        L.Rimg = take(p->Rimg.size());
         L.sig = take(p->sig.size());
         L.dmu = take(p->dmu.size());
         L.Sj = take(p->Sj.size());
@@ -473,8 +523,9 @@ extern "C" spp_status spp_plan_set_path(spp_plan p, spp_path path)
         return spp_fail(SPP_EINVAL, "spp_plan_set_path: unknown path");
     if (path == SPP_PATH_FUSED && !p->fused_ok)
         return spp_fail(SPP_ENOTSUP, "spp_plan_set_path: the fused per-mode path needs an equator-symmetric "
-                                     "theta grid with N_theta % 4 == 0, N_theta <= 128 and N_r <= " +
-                                         std::to_string(modalimg::NRMAX));
+                                     "theta grid with N_theta % 4 == 0, N_theta <= 128, N_r <= " +
+                                         std::to_string(modalimg::NRMAX) +
+                                         " and radial pivot products within its range");
     p->path.store(path);
     return SPP_OK;
 }
@@ -518,6 +569,7 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.Hpar, p->Hpar);
     put(p->lay.Fimg, p->Fimg);
     put(p->lay.Iimg, p->Iimg);
+    put(p->lay.Rimg, p->Rimg);
     put(p->lay.sig, p->sig);
     put(p->lay.dmu, p->dmu);
     put(p->lay.Sj, p->Sj);

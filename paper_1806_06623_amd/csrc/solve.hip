@@ -518,7 +518,8 @@ bool launch_radial_part(double* Y, const double* lam, const double* beta, const 
 
 // Fused per-mode kernel (projection, radial solves, inverse projection) on
 // the folded spectrum X, in place; false when the grid is outside its range.
-bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* lam, const double* beta,
+bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* Rimg, const double* lam,
+                  const double* beta,
                   const radial::Coef& cf, int nr, int nth, int nphi, hipStream_t s)
 {
     const int h = nth / 2;
@@ -528,7 +529,7 @@ bool launch_modal(double* X, const double* Fimg, const double* Iimg, const doubl
     const dim3 grid(2 * nphi), block(modal::THREADS);   // one workgroup per (q, parity), see modal::unit_of
 #define SPP_MODAL(RN, TT)                                                                                      \
     case RN * 4 + TT:                                                                                          \
-        hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, lam, beta, cf, nth, nphi); \
+        hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, Rimg, lam, beta, cf, nth, nphi); \
         return true;
     switch (rn * 4 + T) {
         SPP_MODAL(1, 1)
@@ -763,7 +764,8 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s, true, nth))
             return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
         mark(1);
-        if (!launch_modal(X, Fimg, Iimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, s))
+        const double* Rimg = reinterpret_cast<const double*>(base + p->lay.Rimg);
+        if (!launch_modal(X, Fimg, Iimg, Rimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, s))
             return spp_fail(SPP_ENOTSUP, "spp_solve: grid outside the fused kernel's range");
         mark(2);
         mark(3);
