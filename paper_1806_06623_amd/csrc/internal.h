@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "modal_layout.h"
 #include "sphpoisson.h"
 
 struct spp_grid_s {
@@ -94,4 +95,10 @@ bool spp_tridiag_eigen(int n, std::vector<double>& d, std::vector<double> e, std
 // projection + radial + inverse projection, folded inverse FFT).
 inline bool spp_plan_fused(const spp_plan_s* p) { return p->fused_ok && p->path.load() != SPP_PATH_STAGED; }
 
-inline size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace bytes after the two fields of an FP64 solve that the fused
+// per-mode kernel uses as the sink of its stores of padding rows and columns:
+// one double per thread of its workgroup, shared by all its workgroups
+// (nothing reads them).
+constexpr size_t spp_modal_sink_bytes = spp_align256(size_t(modalimg::NW) * 64 * sizeof(double));

@@ -15,7 +15,10 @@
 // the last h the odd fold s_k - s_{N-1-k} (written by the folded forward
 // FFT); on exit they hold G_e and G_o with g_k = G_e + G_o and
 // g_{N-1-k} = G_e - G_o (undone by the unfolding inverse FFT).  Each
-// workgroup reads and writes only its own half rows.
+// workgroup reads and writes only its own half rows.  `sink` (THREADS
+// doubles, shared by all workgroups and never read, in the same allocation as
+// X and less than 4 GB after it) receives the stores of padding rows and
+// columns.
 //
 // Work split (NW = 12 waves, T row tiles of 16 per wave, CH = 4 T):
 //   wave w, lane (lr = lane % 16, g = lane / 16), accumulator register v of
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
                                                    const double* __restrict__ Iimg, const double* __restrict__ Rimg,
                                                    const double* __restrict__ lam,
                                                    const double* __restrict__ beta, radial::Coef tab, int nth,
-                                                   int nphi)
+                                                   int nphi, double* __restrict__ sink)
 {
     using Gm = Geo<RN>;
     constexpr int NC = Gm::NC, ELEMS = Gm::ELEMS;
@@ -639,6 +642,14 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     MODAL_PHASE_FENCE();
     double* tb = un + w * 16 * TP;
     const int lni = lane_now(), lri = lni & 15, gi = lni >> 4;   // inverse phase
+    // Stores without branches (branches around them would split the code into
+    // blocks the scheduler cannot interleave): every store addresses the
+    // unit's base with a 32-bit byte offset, and the values of padding rows
+    // and columns go to this lane's slot of the sink instead (the sink follows
+    // the field in the same workspace; its slots are shared by all workgroups
+    // and never read).
+    char* const xbase = reinterpret_cast<char*>(Xq);
+    const unsigned sink_off = unsigned(reinterpret_cast<char*>(sink) - xbase) + unsigned(w * 64 + lni) * 8u;
 #pragma unroll
     for (int rb = 0; rb < T; ++rb) {
         d4 out[RN];
@@ -675,7 +686,8 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int R = w * 16 * T + gi * CH + 4 * rb + v;
-                if (R < nr && j < h) Xq[size_t(R) * nth + j] = out[cb][v];
+                const unsigned off = (R < nr && j < h) ? unsigned(R * nth + j) * 8u : sink_off;
+                *reinterpret_cast<double*>(xbase + off) = out[cb][v];
             }
         }
     }

@@ -488,7 +488,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.lamphi = take(p->lamphi.size());
         L.total = off;
         const size_t field = spp_align256(size_t(nr) * nth * nphi * sizeof(double));
-        p->workspace_bytes = 2 * field;
+        // two fields; the fused per-mode kernel also needs its store sink
+        p->workspace_bytes = 2 * field + (p->fused_ok ? spp_modal_sink_bytes : 0);
     } catch (const std::bad_alloc&) {
         delete p;
         return spp_fail(SPP_ENOMEM, "spp_plan_create: out of host memory");

@@ -519,8 +519,8 @@ bool launch_radial_part(double* Y, const double* lam, const double* beta, const 
 // Fused per-mode kernel (projection, radial solves, inverse projection) on
 // the folded spectrum X, in place; false when the grid is outside its range.
 bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* Rimg, const double* lam,
-                  const double* beta,
-                  const radial::Coef& cf, int nr, int nth, int nphi, hipStream_t s)
+                  const double* beta, const radial::Coef& cf, int nr, int nth, int nphi, double* sink,
+                  hipStream_t s)
 {
     const int h = nth / 2;
     const int rn = modalimg::rn_for(h);
@@ -529,7 +529,8 @@ bool launch_modal(double* X, const double* Fimg, const double* Iimg, const doubl
     const dim3 grid(2 * nphi), block(modal::THREADS);   // one workgroup per (q, parity), see modal::unit_of
 #define SPP_MODAL(RN, TT)                                                                                      \
     case RN * 4 + TT:                                                                                          \
-        hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, Rimg, lam, beta, cf, nth, nphi); \
+        hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, Rimg, lam, beta, cf, nth, nphi, \
+                           sink);                                                                              \
         return true;
     switch (rn * 4 + T) {
         SPP_MODAL(1, 1)
@@ -765,7 +766,14 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
             return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
         mark(1);
         const double* Rimg = reinterpret_cast<const double*>(base + p->lay.Rimg);
-        if (!launch_modal(X, Fimg, Iimg, Rimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, s))
+        // the workspace's region after its two fields is the sink of the
+        // per-mode kernel's stores of padding rows and columns
+        static_assert(modal::THREADS * sizeof(double) <= spp_modal_sink_bytes, "sink of one workgroup");
+        // the kernel reaches the sink by 32-bit byte offsets from each unit's rows
+        if (2 * field + spp_modal_sink_bytes > (size_t(1) << 32))
+            return spp_fail(SPP_ENOTSUP, "spp_solve: field too large for the fused kernel");
+        double* sink = reinterpret_cast<double*>(static_cast<char*>(ws) + 2 * field);
+        if (!launch_modal(X, Fimg, Iimg, Rimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, sink, s))
             return spp_fail(SPP_ENOTSUP, "spp_solve: grid outside the fused kernel's range");
         mark(2);
         mark(3);

@@ -131,3 +131,27 @@ def test_fused_path_range_guard():
     eps = 1e-6
     th = np.concatenate(([0.0, eps], np.linspace(eps, np.pi - eps, 15)[1:-1], [np.pi - eps, np.pi]))
     assert _host_path(r_if, th, 64) == STAGED
+
+
+def test_workspace_holds_the_fused_kernels_store_sink():
+    """A fused plan's FP64 workspace is its two fields plus the per-mode
+    kernel's store sink (one double per thread of its 768-thread workgroup);
+    a staged-only plan needs the two fields."""
+    def ws_bytes(r_if, th_if, nphi):
+        st, g = make_grid(r_if, th_if, nphi)
+        _check(st, "grid")
+        p = _vp()
+        _check(lib.spp_plan_create(g, ctypes.byref(p)), "plan")
+        pb, wb = spp._binding._c_size_t(), spp._binding._c_size_t()
+        _check(lib.spp_plan_device_bytes(p, ctypes.byref(pb), ctypes.byref(wb)), "bytes")
+        v = ctypes.c_int()
+        _check(lib.spp_plan_get_path(p, ctypes.byref(v)), "path")
+        lib.spp_plan_destroy(p)
+        lib.spp_grid_destroy(g)
+        return wb.value, v.value
+    field = 256                                   # 2 x 4 x 4 doubles, 256-byte aligned
+    wb, path = ws_bytes(np.array([0.0, 1.0, 2.0]), synthetic.theta_interfaces(4), 4)
+    assert path == 2 and wb == 2 * field + 768 * 8
+    th_ns = np.array([0.0, 0.5, 1.9, np.pi])      # not equator-symmetric: staged only
+    wb, path = ws_bytes(np.array([0.0, 1.0, 2.0]), th_ns, 4)
+    assert path == 1 and wb == 2 * 256
