@@ -157,7 +157,7 @@ spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double 
 spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, size_t* bytes);
 
 /*
- * Mixed-precision solve with iterative refinement (spec production
+ * Mixed-precision solve with iterative refinement (the production
  * form; the operator and its exact solution are those of spp_solve).
  *   s~ = FFT(4 pi G rho) in FP64, once;
  *   g  = H F^-1 H^-1 s~ with the theta projections (Sec. 3.2) as FP32 MFMA

@@ -22,6 +22,10 @@ Poisson equation on 3D spherical polar grids"):
                     boundary term, for residuals and backward errors.
 * ``analytic``   -- closed forms used as pins (uniform sphere, the l=0
                     cumulative-mass recurrence).
+* ``fluxes``     -- the face fluxes of grad Phi through every cell face (the
+                    terms of the flux form of Sec. 3.1, with the outer
+                    boundary face of Sec. 3.2), from which conservative
+                    gravitational source terms are built.
 
 Everything is float64 numpy; scipy supplies the symmetric tridiagonal
 eigensolver and numpy the real FFT (library primitives used as single steps).

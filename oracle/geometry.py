@@ -6,7 +6,7 @@ Indices here are 0-based: radial cells i = 0..nr-1 (paper i = 1..N_r),
 theta cells j = 0..nth-1, phi cells k = 0..nphi-1.  Interface arrays have one
 more entry than the cells they bound.
 
-Readings of the paper's text used here (each listed in the design doc):
+Readings of the paper's text used here:
 * the radial and theta interface areas carry (r_{i+1/2}^2 - r_{i-1/2}^2)/2;
   the printed formula repeats r_{i+1/2} and would be identically zero;
 * cell centres are arithmetic midpoints of their interfaces (this reproduces

@@ -18,7 +18,7 @@ Steps, in the paper's order:
   6. inverse projection g_{ijm} = sum_l H_{l,m}(j) f_{ilm};
   7. inverse FFT of g along phi.
 
-Readings (listed in DESIGN.md):
+Readings of the paper's text used here:
 * hat-Delta_theta carries the factor 1/dmu_j that delta V contributes; without
   it the operator would not be the theta part of the flux form divided by R_i;
 * hat-Delta_phi is the second difference divided by dphi^2, and its eigenvalue

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import analytic, dense, geometry, laplacian, spectral
+from oracle import analytic, dense, fluxes, geometry, laplacian, spectral
 import synthetic
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -207,6 +207,123 @@ def test_shift_and_reflection_equivariance():
     phi = plan.solve(rho)
     assert rel(plan.solve(np.roll(rho, 3, axis=2)), np.roll(phi, 3, axis=2)) < 1e-13
     assert rel(plan.solve(rho[:, ::-1, :]), phi[:, ::-1, :]) < 1e-12
+
+
+# ------------------------------------------------------------ face fluxes
+def _cell_balance_by_loops(r_if, th_if, nphi, Fr, Ft, Fp):
+    """Net outward flux of every cell, summed face by face (brute force)."""
+    nr, nth = len(r_if) - 1, len(th_if) - 1
+    out = np.zeros((nr, nth, nphi))
+    for i in range(nr):
+        for j in range(nth):
+            for k in range(nphi):
+                v = Fr[i, j, k] + Ft[i, j, k] + Fp[i, j, k]      # outer r, theta, phi faces
+                if i > 0:
+                    v -= Fr[i - 1, j, k]
+                if j > 0:
+                    v -= Ft[i, j - 1, k]
+                v -= Fp[i, j, (k - 1) % nphi]
+                out[i, j, k] = v
+    return out
+
+
+def _cell_volumes_full(r_if, th_if, nphi):
+    r_if, th_if = np.asarray(r_if), np.asarray(th_if)
+    v = np.outer((r_if[1:] ** 3 - r_if[:-1] ** 3) / 3.0, np.cos(th_if[:-1]) - np.cos(th_if[1:]))
+    return v[:, :, None] * (2.0 * np.pi / nphi)
+
+
+@pytest.mark.parametrize("nr,nth,nphi,r0,uni", CASES)
+def test_face_fluxes_gauss_law_per_cell(nr, nth, nphi, r0, uni):
+    """For the exact discrete solution (dense direct solve of the operator
+    assembled from the flux form), the six face fluxes of every cell add up
+    to 4 pi G rho delta V (Gauss's law on the grid)."""
+    rng = np.random.default_rng(nr * 100 + nth * 10 + nphi + 1)
+    r_if = random_r_if(rng, nr, r0)
+    th_if = synthetic.theta_interfaces(nth) if uni else random_th_if(rng, nth)
+    rho = rng.standard_normal((nr, nth, nphi))
+    G = 0.7
+    phi = dense.solve(r_if, th_if, nphi, rho, G=G)
+    Fr, Ft, Fp = fluxes.face_fluxes(r_if, th_if, nphi, phi)
+    src = 4.0 * np.pi * G * rho * _cell_volumes_full(r_if, th_if, nphi)
+    bal = _cell_balance_by_loops(r_if, th_if, nphi, Fr, Ft, Fp)
+    assert np.max(np.abs(bal - src)) < 1e-12 * np.max(np.abs(src))
+    assert np.max(np.abs(fluxes.net_outward_flux(Fr, Ft, Fp) - bal)) < 1e-14 * np.max(np.abs(src))
+    assert np.all(Ft[:, -1, :] == 0.0)           # pole face theta = pi
+
+
+def test_face_fluxes_spherical_closed_form():
+    """A spherically symmetric source: the radial flux through the sphere
+    r_{i+1/2}, per unit of dmu dphi, is 4 pi G times the enclosed mass over
+    4 pi (the enclosed mass sum_{i' <= i} rho_{i'} 4 pi (r_+^3 - r_-^3)/3);
+    the outer face carries the total; theta and phi fluxes vanish."""
+    nr, nth, nphi, G = 128, 16, 8, 1.3
+    r_if = synthetic.stellar_r_interfaces(nr)
+    th_if = synthetic.theta_interfaces(nth)
+    r = 0.5 * (r_if[:-1] + r_if[1:])
+    rho_r = (1 + (r / 20.0) ** 2) ** -1.5
+    phi_r = analytic.spherical_discrete_potential(r_if, 4 * np.pi * G * rho_r)
+    phi = np.broadcast_to(phi_r[:, None, None], (nr, nth, nphi)).copy()
+    Fr, Ft, Fp = fluxes.face_fluxes(r_if, th_if, nphi, phi)
+    m_enc = np.cumsum(rho_r * 4.0 * np.pi * (r_if[1:] ** 3 - r_if[:-1] ** 3) / 3.0)
+    dmu = np.cos(th_if[:-1]) - np.cos(th_if[1:])
+    want = G * m_enc[:, None, None] * dmu[None, :, None] * (2.0 * np.pi / nphi) * np.ones((1, 1, nphi))
+    assert rel(Fr, want) < 1e-12
+    assert np.max(np.abs(Ft)) == 0.0 and np.max(np.abs(Fp)) == 0.0
+
+
+def test_face_fluxes_total_outer_flux_is_enclosed_mass():
+    """Off-centre source on a stellar grid: the outer-face fluxes sum to
+    4 pi G M (global Gauss's law), and every cell balances."""
+    c = synthetic.stellar_case(nr=96, nth=32, nphi=32, seed=5)
+    G = 1.0
+    phi = spectral.solve(c["r_if"], c["th_if"], c["nphi"], c["rho"], G=G)
+    Fr, Ft, Fp = fluxes.face_fluxes(c["r_if"], c["th_if"], c["nphi"], phi)
+    dV = _cell_volumes_full(c["r_if"], c["th_if"], c["nphi"])
+    mass = float(np.sum(c["rho"] * dV))
+    assert abs(Fr[-1].sum() - 4.0 * np.pi * G * mass) < 1e-12 * 4.0 * np.pi * G * mass
+    src = 4.0 * np.pi * G * c["rho"] * dV
+    bal = fluxes.net_outward_flux(Fr, Ft, Fp)
+    # per cell, on the scale of the componentwise backward error:
+    # |L| |Phi| delta V + |s| delta V
+    _, mag = laplacian.apply(c["r_if"], c["th_if"], c["nphi"], phi, with_terms=True)
+    assert np.max(np.abs(bal - src) / (mag * dV + np.abs(src))) < 1e-13
+
+
+def test_face_fluxes_constant_potential():
+    """Phi = c: no flux through interior faces; the constant is the exact
+    (l, m) = (0, 0) eigenmode (lambda = 0, exponent p = 1), so the outer face
+    carries -c r_N dmu_j dphi with r_N the outermost cell centre."""
+    rng = np.random.default_rng(21)
+    r_if, th_if, nphi, c = random_r_if(rng, 6, 1.0), random_th_if(rng, 8), 12, -2.5
+    Fr, Ft, Fp = fluxes.face_fluxes(r_if, th_if, nphi, np.full((6, 8, nphi), c))
+    rN = 0.5 * (r_if[-2] + r_if[-1])
+    dmu = np.cos(th_if[:-1]) - np.cos(th_if[1:])
+    want = -c * rN * dmu[:, None] * (2.0 * np.pi / nphi) * np.ones((1, nphi))
+    assert np.all(Fr[:-1] == 0.0) and np.all(Ft == 0.0) and np.all(Fp == 0.0)
+    assert rel(Fr[-1], want) < 1e-13
+
+
+def test_face_flux_pins_catch_planted_mistakes(monkeypatch):
+    """Slips in the outer-face term fail the Gauss-law pin."""
+    rng = np.random.default_rng(5)
+    r_if, th_if, nphi = random_r_if(rng, 5), random_th_if(rng, 4), 6
+    rho = rng.standard_normal((5, 4, nphi))
+    phi = dense.solve(r_if, th_if, nphi, rho)
+    src = 4.0 * np.pi * rho * _cell_volumes_full(r_if, th_if, nphi)
+
+    def ok():
+        F = fluxes.face_fluxes(r_if, th_if, nphi, phi)
+        return np.max(np.abs(_cell_balance_by_loops(r_if, th_if, nphi, *F) - src)) < 1e-12 * np.max(np.abs(src))
+
+    assert ok()
+    orig = fluxes.outer_flux
+    for slip in (lambda g, s: -orig(g, s), lambda g, s: orig(g, s) * g["r"][-1] / g["r_if"][-1],
+                 lambda g, s: orig(g, s[:, ::-1])):
+        monkeypatch.setattr(fluxes, "outer_flux", slip)
+        assert not ok()
+        monkeypatch.undo()
+    assert ok()
 
 
 # --------------------------------------------------- sensitivity of the pins
