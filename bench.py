@@ -225,6 +225,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-fluxes", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--n-refine", type=int, default=1)
     ap.add_argument("--nr", type=int, default=550)
@@ -363,6 +364,29 @@ def main():
                  "max_rel_diff_vs_fp64_gpu": d, "speedup_vs_fp64": round(elapsed / el_m, 3)}
         log(f"mixed: {el_m * 1e3 / K:.3f} ms/solve, diff vs FP64 {d:.2e}")
 
+    # face fluxes of grad Phi (spp_face_fluxes) of the solution just computed:
+    # one read of Phi and three fields written, HBM-bound
+    face = None
+    if not args.no_fluxes:
+        fl = tuple(torch.empty_like(phi) for _ in range(3))
+        for _ in range(min(args.warmup, 20)):
+            plan.face_fluxes(phi, out=fl)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            plan.face_fluxes(phi, out=fl)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        fbytes = 4 * 8.0 * zones
+        face = {"ms": round(ms, 5), "alg_bytes": fbytes, "GBps": round(fbytes / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(fbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "whole entry point: outer-shell boundary term (shell FFT, per-mode beta, inverse "
+                        "FFT) and the flux stencil; algorithmic bytes = Phi read once + three flux fields"}
+        log(f"face fluxes: {ms * 1e3:.1f} us per call, {face['GBps']} GB/s")
+        del fl
+
     batch = None if args.no_batch else batched_leg(spp, torch, synthetic, args.batch_steps)
     serving = None if args.no_serving else serving_leg(spp, torch, synthetic, args.serving_requests,
                                                         (0.5, 0.8, 0.95))
@@ -382,6 +406,7 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "mixed": mixed,
+        "face_fluxes": face,
         "batched": batch,
         "serving": serving,
     }

@@ -150,6 +150,38 @@ spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double 
                      void* workspace_dev, void* stream);
 
 /*
+ * Face fluxes of grad Phi through every cell face, enqueued on `stream`
+ * (Sec. 3.1: the operator is a finite-volume divergence, (Delta Phi) delta V =
+ * the sum over a cell's six faces of area x difference quotient; Sec. 3.2 for
+ * the outer boundary face).  For Phi from spp_solve the six fluxes of every
+ * cell add up to 4 pi G rho delta V to rounding (Gauss's law on the grid):
+ * the building block of gravitational momentum and energy source terms in
+ * conservative form (Sec. 1, Sec. 3.1).  Each flux is signed along its
+ * increasing coordinate:
+ *   fr_dev[i][j][k]  face i+1/2:  r_{i+1/2}^2 dmu_j dphi (Phi_{i+1} - Phi_i)/(r_{i+1} - r_i);
+ *                    i = N_r - 1 is the outer boundary face, dmu_j dphi times
+ *                    the extrapolated derivative of the asymptotic condition,
+ *                    applied per (l, m) mode of the outermost shell;
+ *   ft_dev[i][j][k]  face j+1/2:  (r_{i+1/2}^2 - r_{i-1/2}^2)/2 sin th_{j+1/2} dphi
+ *                    (Phi_{j+1} - Phi_j)/(r_i (th_{j+1} - th_j)); 0 at j = N_theta - 1 (pole);
+ *   fp_dev[i][j][k]  face k+1/2:  (r_{i+1/2}^2 - r_{i-1/2}^2)/2 (th_{j+1/2} - th_{j-1/2})
+ *                    (Phi_{k+1} - Phi_k)/(r_i sin th_j dphi); k + 1 wraps to 0;
+ * with dmu_j = cos th_{j-1/2} - cos th_{j+1/2}, dphi = 2 pi / N_phi and cell
+ * centres at interface midpoints.  The faces r = 0 and theta = 0 have zero
+ * area and are not stored.
+ *   phi_dev        device, [N_r][N_theta][N_phi] float64, read-only;
+ *   fr/ft/fp_dev   device, same shape each, written;
+ *   workspace_dev  device scratch of the plan's workspace_bytes (256-byte aligned).
+ * All four fields 16-byte aligned and pairwise disjoint.  The call reads the
+ * plan's uploaded tables and allocates nothing.
+ * Errors (synchronous, nothing enqueued): SPP_EINVAL (NULL, misaligned,
+ * overlap), SPP_ESTATE (plan not uploaded), SPP_ENOTSUP (N_theta > 1920),
+ * SPP_EDEVICE (launch failure).
+ */
+spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double* fr_dev, double* ft_dev, double* fp_dev,
+                           void* workspace_dev, void* stream);
+
+/*
  * Workspace bytes of one solve in flight for a given precision (SPP_FP64: as
  * spp_plan_device_bytes; SPP_MIXED_FP32: four fields plus one shell).
  * Errors: SPP_EINVAL (NULL), SPP_ENOTSUP (precision not built).

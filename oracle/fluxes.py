@@ -31,7 +31,7 @@ of the first shell and the pole face theta = 0 have zero area and are not
 stored.  The areas, volumes and centres are those of Sec. 3.1 with the
 readings of ``geometry`` (area factor (r_{i+1/2}^2 - r_{i-1/2}^2)/2, centres
 at interface midpoints); they are computed here from the interfaces, not
-from the solver's factored coefficients.
+from the solver's factored coefficients R_i, S_j.
 """
 import numpy as np
 
@@ -49,8 +49,12 @@ def face_fluxes(r_if, th_if, nphi, Phi):
     r = 0.5 * (r_if[:-1] + r_if[1:])
     th = 0.5 * (th_if[:-1] + th_if[1:])
     dphi = 2.0 * np.pi / nphi
-    dmu = np.cos(th_if[:-1]) - np.cos(th_if[1:])          # cos th_{j-1/2} - cos th_{j+1/2}
-    ring = 0.5 * (r_if[1:] ** 2 - r_if[:-1] ** 2)           # (r_{i+1/2}^2 - r_{i-1/2}^2)/2
+    # cos th_{j-1/2} - cos th_{j+1/2} and (r_{i+1/2}^2 - r_{i-1/2}^2)/2 in
+    # factored form: the same quantities without the cancellation of the plain
+    # differences next to the poles and on thin outer shells
+    tm, tp = th_if[:-1], th_if[1:]
+    dmu = 2.0 * np.sin(0.5 * (tp + tm)) * np.sin(0.5 * (tp - tm))
+    ring = 0.5 * (r_if[1:] - r_if[:-1]) * (r_if[1:] + r_if[:-1])
 
     Fr = np.zeros_like(P)
     area_r = (r_if[1:-1] ** 2)[:, None] * dmu[None, :] * dphi

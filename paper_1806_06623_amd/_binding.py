@@ -37,6 +37,8 @@ lib.spp_solve.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp]
 lib.spp_solve.restype = _c_int
 lib.spp_solve_profiled.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp, _dp]
 lib.spp_solve_profiled.restype = _c_int
+lib.spp_face_fluxes.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+lib.spp_face_fluxes.restype = _c_int
 lib.spp_plan_workspace_bytes.argtypes = [_vp, _c_int, ctypes.POINTER(_c_size_t)]
 lib.spp_plan_workspace_bytes.restype = _c_int
 lib.spp_solve_mixed.argtypes = [_vp, _c_int, _c_int, _vp, _vp, _c_double, _vp, _vp]
@@ -193,6 +195,23 @@ class Plan:
         _check(lib.spp_solve(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
                              _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_solve")
         return out
+
+    def face_fluxes(self, phi, out=None, workspace=None, stream=None):
+        """Face fluxes (Fr, Ft, Fp) of grad Phi through the r, theta and phi
+        faces of every cell (see spp_face_fluxes); three float64 tensors of
+        Phi's shape, written on the current torch stream."""
+        import torch
+        if phi.dtype != torch.float64 or not phi.is_contiguous() or tuple(phi.shape) != self.shape:
+            raise ValueError(f"phi must be a contiguous float64 tensor of shape {self.shape}")
+        if phi.device != self.device:
+            raise ValueError("phi must live on the plan's device")
+        if out is None:
+            out = tuple(torch.empty_like(phi) for _ in range(3))
+        fr, ft, fp = out
+        ws = self.workspace if workspace is None else workspace
+        _check(lib.spp_face_fluxes(self._plan, _vp(phi.data_ptr()), _vp(fr.data_ptr()), _vp(ft.data_ptr()),
+                                   _vp(fp.data_ptr()), _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_face_fluxes")
+        return fr, ft, fp
 
     def workspace_bytes_for(self, precision):
         b = _c_size_t()

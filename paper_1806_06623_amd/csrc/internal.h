@@ -78,6 +78,11 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision prec, int n
 // Workspace of the mixed-precision solve: four fields and one outer shell.
 size_t spp_mixed_workspace_bytes(const spp_plan_s* p);
 
+// Device entry of the face fluxes of grad Phi (solve.hip); the workspace needs
+// two shells of N_theta N_phi doubles (any FP64 solve workspace holds them).
+spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double* fr, double* ft, double* fp,
+                                  void* ws, void* stream);
+
 // Projection tile autotuner and launch-cache prewarm (solve.hip).
 spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* stream, int* chosen_rm);
 void spp_prewarm_launch_caches(const spp_plan_s* p);

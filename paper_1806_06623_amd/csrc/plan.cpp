@@ -638,6 +638,27 @@ extern "C" spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refi
     return spp_launch_solve_mixed(p, prec, n_refine, rho_dev, phi_dev, G, workspace_dev, stream);
 }
 
+extern "C" spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double* fr_dev, double* ft_dev,
+                                      double* fp_dev, void* workspace_dev, void* stream)
+{
+    if (!p || !phi_dev || !fr_dev || !ft_dev || !fp_dev || !workspace_dev)
+        return spp_fail(SPP_EINVAL, "spp_face_fluxes: NULL pointer");
+    if (!p->dev) return spp_fail(SPP_ESTATE, "spp_face_fluxes: plan not uploaded");
+    if (reinterpret_cast<uintptr_t>(workspace_dev) & 255)
+        return spp_fail(SPP_EINVAL, "spp_face_fluxes: workspace must be 256-byte aligned");
+    const size_t n = size_t(p->nr) * p->nth * p->nphi * sizeof(double);
+    const char* b[4] = {reinterpret_cast<const char*>(phi_dev), reinterpret_cast<const char*>(fr_dev),
+                        reinterpret_cast<const char*>(ft_dev), reinterpret_cast<const char*>(fp_dev)};
+    for (int x = 0; x < 4; ++x) {
+        if (reinterpret_cast<uintptr_t>(b[x]) & 15)
+            return spp_fail(SPP_EINVAL, "spp_face_fluxes: field pointers must be 16-byte aligned");
+        for (int y = x + 1; y < 4; ++y)
+            if (b[x] < b[y] + n && b[y] < b[x] + n)
+                return spp_fail(SPP_EINVAL, "spp_face_fluxes: phi and the three flux fields must not overlap");
+    }
+    return spp_launch_face_fluxes(p, phi_dev, fr_dev, ft_dev, fp_dev, workspace_dev, stream);
+}
+
 extern "C" spp_status spp_autotune_projection(spp_plan p, void* workspace_dev, void* stream, int* chosen_rows)
 {
     if (!p || !workspace_dev) return spp_fail(SPP_EINVAL, "spp_autotune_projection: NULL pointer");

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "fft.hip.h"
+#include "fluxes.hip.h"
 #include "internal.h"
 #include "modal.hip.h"
 #include "proj.hip.h"
@@ -624,40 +625,6 @@ bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64
 // component q is a local operator in (i, j) plus, on the outermost shell, the
 // boundary term of Sec. 3.2, which acts per theta eigenmode.
 
-// ob[q][j] = (H_m diag(beta_m) H_m^-1 g_q[N_r - 1, :])_j, one workgroup per q.
-// With H^-1 = H^T D and H = diag(1/dmu) W^T both sums read the stored
-// matrices along contiguous rows across the threads:
-//   c_l  = beta_l sum_j H[j][l] dmu_j g_j,     ob_j = (1/dmu_j) sum_l W[l][j] c_l.
-__global__ __launch_bounds__(256) void k_outer_bc(const double* __restrict__ Gf, double* __restrict__ ob,
-                                                  const double* __restrict__ W, const double* __restrict__ H,
-                                                  const double* __restrict__ beta, const double* __restrict__ dmu,
-                                                  int nr, int nth, int nphi)
-{
-    extern __shared__ double sh[];   // [2][nth]: weighted shell values, then the coefficients
-    const int q = blockIdx.x;
-    const int m = q <= nphi / 2 ? q : nphi - q;
-    const double* shell = Gf + (size_t(q) * nr + (nr - 1)) * nth;
-    double* gs = sh;
-    double* cs = sh + nth;
-    for (int j = threadIdx.x; j < nth; j += blockDim.x) gs[j] = shell[j] * dmu[j];
-    __syncthreads();
-    const double* Wm = W + size_t(m) * nth * nth;   // [l][j]
-    const double* Hm = H + size_t(m) * nth * nth;   // [j][l]
-    for (int l = threadIdx.x; l < nth; l += blockDim.x) {
-        double c = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < nth; ++j) c += Hm[size_t(j) * nth + l] * gs[j];
-        cs[l] = c * beta[m * nth + l];
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < nth; j += blockDim.x) {
-        double v = 0.0;
-#pragma unroll 8
-        for (int l = 0; l < nth; ++l) v += Wm[size_t(l) * nth + j] * cs[l];
-        ob[size_t(q) * nth + j] = v / dmu[j];
-    }
-}
-
 // r = s~ - L_q g for every element (q, i, j), FP64.
 struct ResidualTables {
     const double* alpha;   // [nr], alpha[nr-1] = 0
@@ -848,8 +815,9 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
     for (int it = 0; it <= n_refine; ++it) {
         const double* src = St;
         if (it > 0) {
-            hipLaunchKernelGGL(k_outer_bc, dim3(nphi), dim3(256), 2 * nth * sizeof(double), s, Gf, ob,
-                               tab(p->lay.W), tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu), nr, nth, nphi);
+            hipLaunchKernelGGL(faceflux::k_outer_modes, dim3(nphi / 2 + 1), dim3(256), (4 * nth + 512) * sizeof(double),
+                               s, Gf + size_t(nr - 1) * nth, size_t(nr) * nth, ob, tab(p->lay.W), tab(p->lay.H),
+                               tab(p->lay.beta), tab(p->lay.dmu), nth, nphi);
             hipLaunchKernelGGL(k_residual, dim3((nlines + 255) / 256, nphi), dim3(256), 0, s, St, Gf, ob, Y, rt,
                                nr, nth, nphi);
             src = Y;
@@ -864,6 +832,40 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
     launch_fft(nphi, false, Gf, phi, tw, 1.0, nlines, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve_mixed: ") + hipGetErrorString(e));
+    return SPP_OK;
+}
+
+// Face fluxes of grad Phi (fluxes.hip.h).  The outer face needs the boundary
+// term of Sec. 3.2 on the outermost shell, T = beta(A) Phi_shell, which acts
+// per angular eigenmode: the shell's Fourier components (forward FFT of its
+// N_theta lines), faceflux::k_outer_modes per mode, and the inverse FFT back to
+// [j][k].  Workspace: two shell-sized buffers (the inverse FFT writes T over
+// the spectrum, which is dead by then).
+spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double* fr, double* ft, double* fp,
+                                  void* ws, void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const char* base = static_cast<const char*>(p->dev);
+    auto tab = [&](size_t off) { return reinterpret_cast<const double*>(base + off); };
+    const c64* tw = reinterpret_cast<const c64*>(base + p->lay.tw);
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    const int plane = nth * nphi;
+    char* w = static_cast<char*>(ws);
+    double* S = reinterpret_cast<double*>(w);                                       // spectrum, then T
+    double* ob = reinterpret_cast<double*>(w + spp_align256(size_t(plane) * sizeof(double)));
+
+    const size_t lds = (4 * size_t(nth) + 512) * sizeof(double);
+    if (lds > 65536) return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: needs N_theta <= 1920");
+    if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, S, tw, 1.0 / nphi, nth, s))
+        return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: unsupported nphi");
+    hipLaunchKernelGGL(faceflux::k_outer_modes, dim3(nphi / 2 + 1), dim3(256), lds, s, S, size_t(nth), ob, tab(p->lay.W), tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu), nth, nphi);
+    launch_fft(nphi, false, ob, S, tw, 1.0, nth, s);
+    const faceflux::Tables t{tab(p->lay.alpha), tab(p->lay.VR), tab(p->lay.sig), tab(p->lay.dmu), tab(p->lay.Sj)};
+    const dim3 grid((plane + faceflux::THREADS - 1) / faceflux::THREADS, (nr + faceflux::ROWS - 1) / faceflux::ROWS);
+    hipLaunchKernelGGL(faceflux::k_face_fluxes, grid, dim3(faceflux::THREADS), 0, s, phi, S, fr, ft, fp, t, nr, nth,
+                       nphi, 2.0 * M_PI / nphi);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_face_fluxes: ") + hipGetErrorString(e));
     return SPP_OK;
 }
 

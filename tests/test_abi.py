@@ -70,6 +70,20 @@ def test_solve_before_upload_is_a_state_error():
     lib.spp_grid_destroy(g)
 
 
+def test_face_fluxes_argument_checks_on_the_host():
+    """NULL pointers are invalid; a plan that was never uploaded is a state
+    error (no kernel is enqueued in either case)."""
+    st, g = make_grid(np.array([0.0, 1.0, 2.0]), synthetic.theta_interfaces(4), 8)
+    p = _vp()
+    _check(lib.spp_plan_create(g, ctypes.byref(p)), "plan")
+    a, b, c, d, w = (ctypes.c_void_p(x) for x in (256, 4096, 8192, 12288, 16384))
+    assert lib.spp_face_fluxes(p, a, b, c, None, w, None) == -1
+    assert lib.spp_face_fluxes(None, a, b, c, d, w, None) == -1
+    assert lib.spp_face_fluxes(p, a, b, c, d, w, None) == -5
+    lib.spp_plan_destroy(p)
+    lib.spp_grid_destroy(g)
+
+
 @pytest.mark.parametrize("nth,nphi,uniform", [(64, 64, True), (128, 256, True), (13, 16, False)])
 def test_host_eigensystems_match_oracle(nth, nphi, uniform):
     """The library's own QL eigensolver against the oracle (LAPACK), compared
