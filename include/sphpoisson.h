@@ -175,7 +175,7 @@ spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double 
  * All four fields 16-byte aligned and pairwise disjoint.  The call reads the
  * plan's uploaded tables and allocates nothing.
  * Errors (synchronous, nothing enqueued): SPP_EINVAL (NULL, misaligned,
- * overlap), SPP_ESTATE (plan not uploaded), SPP_ENOTSUP (N_theta > 1920),
+ * overlap), SPP_ESTATE (plan not uploaded), SPP_ENOTSUP (N_theta > 3840),
  * SPP_EDEVICE (launch failure).
  */
 spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double* fr_dev, double* ft_dev, double* fp_dev,

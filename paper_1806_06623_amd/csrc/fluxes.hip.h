@@ -17,7 +17,9 @@
 // the first store, so each thread keeps ~3 ROWS loads in flight.  The
 // neighbours are rows that adjacent threads load and come from cache.
 // Consecutive threads run along phi, so every load and store of a wave
-// covers 512 contiguous bytes.
+// covers 512 contiguous bytes.  The flux fields are stored non-temporally
+// (three times the size of Phi, nothing rereads them here), which keeps them
+// from evicting the rows of Phi that neighbouring workgroups still read.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -25,7 +27,7 @@ namespace faceflux {
 
 constexpr int THREADS = 256;
 constexpr int ROWS = 8;    // radial rows per thread (k_face_fluxes)
-constexpr int BATCH = 16;  // matrix loads in flight per thread (k_outer_modes)
+constexpr int BATCH = 16;  // matrix loads in flight per thread (k_outer_coef, k_outer_apply)
 
 struct Tables {
     const double* alpha;   // [N_r], alpha[N_r - 1] = 0
@@ -74,9 +76,9 @@ __global__ __launch_bounds__(THREADS) void k_face_fluxes(const double* __restric
         if (i < nr) {
             const size_t at = size_t(i) * plane + e;
             const double vr = t.VR[i];
-            fr[at] = i + 1 < nr ? t.alpha[i] * cr * (c[r + 1] - c[r]) : -cr * ob;
-            ft[at] = vr * ct * (nj[r] - c[r]);
-            fp[at] = vr * cp * (nk[r] - c[r]);
+            __builtin_nontemporal_store(i + 1 < nr ? t.alpha[i] * cr * (c[r + 1] - c[r]) : -cr * ob, fr + at);
+            __builtin_nontemporal_store(vr * ct * (nj[r] - c[r]), ft + at);
+            __builtin_nontemporal_store(vr * cp * (nk[r] - c[r]), fp + at);
         }
     }
 }
@@ -84,82 +86,115 @@ __global__ __launch_bounds__(THREADS) void k_face_fluxes(const double* __restric
 // Outer boundary term of Sec. 3.2 on the outermost shell, per Fourier mode m:
 //   ob_q = H_m diag(beta_m) H_m^T D g_q
 // for the components q = m and q = N_phi - m of m (one component for m = 0
-// and m = N_phi / 2), one workgroup per m, so both components share one pass
-// over the stored matrices (W_m = H_m^T D, so H_m = diag(1/dmu) W_m^T):
-//   c_l  = beta_l sum_j H[j][l] dmu_j g_j,     ob_j = (1/dmu_j) sum_l W[l][j] c_l.
-// Each sum is split over 256 / (outputs) threads, reading the matrices along
-// contiguous rows, and reduced in LDS.  g_q starts at g + q gq, ob_q at
-// ob + q N_theta.  Dynamic LDS: (4 N_theta + 512) doubles.
-__global__ __launch_bounds__(256) void k_outer_modes(const double* __restrict__ g, size_t gq,
-                                                     double* __restrict__ ob, const double* __restrict__ W,
-                                                     const double* __restrict__ H,
-                                                     const double* __restrict__ beta,
-                                                     const double* __restrict__ dmu, int nth, int nphi)
+// and m = N_phi / 2).  With W_m = H_m^T D, i.e. H_m = diag(1/dmu) W_m^T:
+//   k_outer_coef   c_l  = beta_l sum_j H[j][l] dmu_j g_j
+//   k_outer_apply  ob_j = (1/dmu_j) sum_l W[l][j] c_l
+// Each is a product with the transpose of a stored N_theta x N_theta matrix;
+// workgroup (m, b) computes the 32 outputs 32 b .. 32 b + 31 of both
+// components of m from one pass over 32 columns of the matrix, so the
+// (N_phi/2 + 1) x ceil(N_theta/32) workgroups share the matrix bytes.
+// Vectors are [q][N_theta] (g_q may be strided: g + q gq).  Dynamic LDS:
+// (2 N_theta + 512) doubles.
+
+// y = A^T x for the 32 outputs o0 .. o0 + 31 and two vectors x0, x1 (LDS):
+// thread (o, sp) = (tid % 32, tid / 32) sums the rows x = sp, sp + 8, ...
+// with BATCH loads in flight, and the 8 partial sums meet in LDS.  Columns
+// past N_theta are clamped for the loads and their results dropped.
+__device__ __forceinline__ void cols32(const double* __restrict__ A, const double* x0, const double* x1, int o0,
+                                       int nth, double* part, double& y0, double& y1)
 {
-    extern __shared__ double sh[];
-    double* gs = sh;               // [2][nth]  dmu-weighted inputs
-    double* cs = sh + 2 * nth;     // [2][nth]  coefficients
-    double* part = sh + 4 * nth;   // [2][256]  partial sums
-    const int m = blockIdx.x;
-    const bool two = m > 0 && 2 * m < nphi;
-    const int q1 = nphi - m;
-    const int tid = threadIdx.x;
-    for (int j = tid; j < nth; j += 256) {
-        gs[j] = g[size_t(m) * gq + j] * dmu[j];
-        gs[nth + j] = two ? g[size_t(q1) * gq + j] * dmu[j] : 0.0;
+    const int tid = threadIdx.x, o = tid & 31, sp = tid >> 5;
+    const int col = min(o0 + o, nth - 1);
+    double a0 = 0.0, a1 = 0.0;
+    for (int xb = sp; xb < nth; xb += 8 * BATCH) {
+        double a[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int x = xb + 8 * u;
+            a[u] = x < nth ? A[size_t(x) * nth + col] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int x = min(xb + 8 * u, nth - 1);   // a[u] = 0 past the end
+            a0 += a[u] * x0[x];
+            a1 += a[u] * x1[x];
+        }
     }
+    part[sp * 32 + o] = a0;
+    part[256 + sp * 32 + o] = a1;
     __syncthreads();
-    const double* Hm = H + size_t(m) * nth * nth;   // [j][l]
-    const double* Wm = W + size_t(m) * nth * nth;   // [l][j]
-    for (int pass = 0; pass < 2; ++pass) {
-        const double* A = pass == 0 ? Hm : Wm;      // both read as A[x][o] for output o
-        const double* in = pass == 0 ? gs : cs;
-        for (int base = 0; base < nth; base += 256) {
-            const int nout = min(256, nth - base);
-            const int S = 256 / nout;
-            const int o = tid % nout, sp = tid / nout;
-            if (sp < S) {
-                // BATCH independent matrix loads in flight per thread (the
-                // sums are latency-bound otherwise: 129 workgroups at N_phi = 256)
-                double a0 = 0.0, a1 = 0.0;
-                for (int x0 = sp; x0 < nth; x0 += BATCH * S) {
-                    double a[BATCH];
-#pragma unroll
-                    for (int u = 0; u < BATCH; ++u) {
-                        const int x = x0 + u * S;
-                        a[u] = x < nth ? A[size_t(x) * nth + base + o] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < BATCH; ++u) {
-                        const int x = min(x0 + u * S, nth - 1);   // a[u] = 0 past the end
-                        a0 += a[u] * in[x];
-                        a1 += a[u] * in[nth + x];
-                    }
-                }
-                part[sp * nout + o] = a0;
-                part[256 + sp * nout + o] = a1;
-            }
-            __syncthreads();
-            if (tid < nout) {
-                double v0 = 0.0, v1 = 0.0;
-                for (int y = 0; y < S; ++y) {
-                    v0 += part[y * nout + tid];
-                    v1 += part[256 + y * nout + tid];
-                }
-                const int idx = base + tid;
-                if (pass == 0) {
-                    const double b = beta[size_t(m) * nth + idx];
-                    cs[idx] = v0 * b;
-                    cs[nth + idx] = v1 * b;
-                } else {
-                    const double w = 1.0 / dmu[idx];
-                    ob[size_t(m) * nth + idx] = v0 * w;
-                    if (two) ob[size_t(q1) * nth + idx] = v1 * w;
-                }
-            }
-            __syncthreads();
+    y0 = 0.0;
+    y1 = 0.0;
+    if (tid < 32) {
+        for (int y = 0; y < 8; ++y) {
+            y0 += part[y * 32 + tid];
+            y1 += part[256 + y * 32 + tid];
         }
     }
 }
+
+__global__ __launch_bounds__(256) void k_outer_coef(const double* __restrict__ g, size_t gq,
+                                                    double* __restrict__ c, const double* __restrict__ H,
+                                                    const double* __restrict__ beta,
+                                                    const double* __restrict__ dmu, int nth, int nphi)
+{
+    extern __shared__ double sh[];
+    double* x0 = sh;
+    double* x1 = sh + nth;
+    const int m = blockIdx.x, o0 = blockIdx.y * 32;
+    const bool two = m > 0 && 2 * m < nphi;
+    const int q1 = nphi - m;
+    for (int j = threadIdx.x; j < nth; j += 256) {
+        x0[j] = g[size_t(m) * gq + j] * dmu[j];
+        x1[j] = two ? g[size_t(q1) * gq + j] * dmu[j] : 0.0;
+    }
+    __syncthreads();
+    double y0, y1;
+    cols32(H + size_t(m) * nth * nth, x0, x1, o0, nth, sh + 2 * nth, y0, y1);
+    const int l = o0 + int(threadIdx.x);
+    if (threadIdx.x < 32 && l < nth) {
+        const double b = beta[size_t(m) * nth + l];
+        c[size_t(m) * nth + l] = y0 * b;
+        if (two) c[size_t(q1) * nth + l] = y1 * b;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_outer_apply(const double* __restrict__ c, double* __restrict__ ob,
+                                                     const double* __restrict__ W,
+                                                     const double* __restrict__ dmu, int nth, int nphi)
+{
+    extern __shared__ double sh[];
+    double* x0 = sh;
+    double* x1 = sh + nth;
+    const int m = blockIdx.x, o0 = blockIdx.y * 32;
+    const bool two = m > 0 && 2 * m < nphi;
+    const int q1 = nphi - m;
+    for (int l = threadIdx.x; l < nth; l += 256) {
+        x0[l] = c[size_t(m) * nth + l];
+        x1[l] = two ? c[size_t(q1) * nth + l] : 0.0;
+    }
+    __syncthreads();
+    double y0, y1;
+    cols32(W + size_t(m) * nth * nth, x0, x1, o0, nth, sh + 2 * nth, y0, y1);
+    const int j = o0 + int(threadIdx.x);
+    if (threadIdx.x < 32 && j < nth) {
+        const double w = 1.0 / dmu[j];
+        ob[size_t(m) * nth + j] = y0 * w;
+        if (two) ob[size_t(q1) * nth + j] = y1 * w;
+    }
+}
+
+// Both steps on `stream`; c is a scratch vector set of N_phi N_theta doubles.
+inline void launch_outer(const double* g, size_t gq, double* c, double* ob, const double* W, const double* H,
+                         const double* beta, const double* dmu, int nth, int nphi, hipStream_t s)
+{
+    const dim3 grid(nphi / 2 + 1, (nth + 31) / 32);
+    const size_t lds = (2 * size_t(nth) + 512) * sizeof(double);
+    hipLaunchKernelGGL(k_outer_coef, grid, dim3(256), lds, s, g, gq, c, H, beta, dmu, nth, nphi);
+    hipLaunchKernelGGL(k_outer_apply, grid, dim3(256), lds, s, c, ob, W, dmu, nth, nphi);
+}
+
+// LDS bound of launch_outer: (2 N_theta + 512) doubles within 64 KB.
+constexpr int OUTER_NTH_MAX = (65536 / 8 - 512) / 2;
 
 }  // namespace faceflux

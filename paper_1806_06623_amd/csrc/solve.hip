@@ -815,9 +815,9 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
     for (int it = 0; it <= n_refine; ++it) {
         const double* src = St;
         if (it > 0) {
-            hipLaunchKernelGGL(faceflux::k_outer_modes, dim3(nphi / 2 + 1), dim3(256), (4 * nth + 512) * sizeof(double),
-                               s, Gf + size_t(nr - 1) * nth, size_t(nr) * nth, ob, tab(p->lay.W), tab(p->lay.H),
-                               tab(p->lay.beta), tab(p->lay.dmu), nth, nphi);
+            // outer-shell boundary term; Z is free until the projection below
+            faceflux::launch_outer(Gf + size_t(nr - 1) * nth, size_t(nr) * nth, Z, ob, tab(p->lay.W),
+                                   tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu), nth, nphi, s);
             hipLaunchKernelGGL(k_residual, dim3((nlines + 255) / 256, nphi), dim3(256), 0, s, St, Gf, ob, Y, rt,
                                nr, nth, nphi);
             src = Y;
@@ -838,9 +838,9 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
 // Face fluxes of grad Phi (fluxes.hip.h).  The outer face needs the boundary
 // term of Sec. 3.2 on the outermost shell, T = beta(A) Phi_shell, which acts
 // per angular eigenmode: the shell's Fourier components (forward FFT of its
-// N_theta lines), faceflux::k_outer_modes per mode, and the inverse FFT back to
-// [j][k].  Workspace: two shell-sized buffers (the inverse FFT writes T over
-// the spectrum, which is dead by then).
+// N_theta lines), the two per-mode products of faceflux::launch_outer, and
+// the inverse FFT back to [j][k].  Workspace: two shell-sized buffers A, B
+// (A: spectrum, B: coefficients, A: boundary term per component, B: T).
 spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double* fr, double* ft, double* fp,
                                   void* ws, void* stream)
 {
@@ -851,18 +851,19 @@ spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
     const int plane = nth * nphi;
     char* w = static_cast<char*>(ws);
-    double* S = reinterpret_cast<double*>(w);                                       // spectrum, then T
-    double* ob = reinterpret_cast<double*>(w + spp_align256(size_t(plane) * sizeof(double)));
+    double* A = reinterpret_cast<double*>(w);
+    double* B = reinterpret_cast<double*>(w + spp_align256(size_t(plane) * sizeof(double)));
 
-    const size_t lds = (4 * size_t(nth) + 512) * sizeof(double);
-    if (lds > 65536) return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: needs N_theta <= 1920");
-    if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, S, tw, 1.0 / nphi, nth, s))
+    if (nth > faceflux::OUTER_NTH_MAX)
+        return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: needs N_theta <= " + std::to_string(faceflux::OUTER_NTH_MAX));
+    if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, A, tw, 1.0 / nphi, nth, s))
         return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: unsupported nphi");
-    hipLaunchKernelGGL(faceflux::k_outer_modes, dim3(nphi / 2 + 1), dim3(256), lds, s, S, size_t(nth), ob, tab(p->lay.W), tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu), nth, nphi);
-    launch_fft(nphi, false, ob, S, tw, 1.0, nth, s);
+    faceflux::launch_outer(A, size_t(nth), B, A, tab(p->lay.W), tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu),
+                           nth, nphi, s);
+    launch_fft(nphi, false, A, B, tw, 1.0, nth, s);
     const faceflux::Tables t{tab(p->lay.alpha), tab(p->lay.VR), tab(p->lay.sig), tab(p->lay.dmu), tab(p->lay.Sj)};
     const dim3 grid((plane + faceflux::THREADS - 1) / faceflux::THREADS, (nr + faceflux::ROWS - 1) / faceflux::ROWS);
-    hipLaunchKernelGGL(faceflux::k_face_fluxes, grid, dim3(faceflux::THREADS), 0, s, phi, S, fr, ft, fp, t, nr, nth,
+    hipLaunchKernelGGL(faceflux::k_face_fluxes, grid, dim3(faceflux::THREADS), 0, s, phi, B, fr, ft, fp, t, nr, nth,
                        nphi, 2.0 * M_PI / nphi);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_face_fluxes: ") + hipGetErrorString(e));
