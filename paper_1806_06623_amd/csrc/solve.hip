@@ -862,9 +862,10 @@ spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double
                            nth, nphi, s);
     launch_fft(nphi, false, A, B, tw, 1.0, nth, s);
     const faceflux::Tables t{tab(p->lay.alpha), tab(p->lay.VR), tab(p->lay.sig), tab(p->lay.dmu), tab(p->lay.Sj)};
-    const dim3 grid((plane + faceflux::THREADS - 1) / faceflux::THREADS, (nr + faceflux::ROWS - 1) / faceflux::ROWS);
-    hipLaunchKernelGGL(faceflux::k_face_fluxes, grid, dim3(faceflux::THREADS), 0, s, phi, B, fr, ft, fp, t, nr, nth,
-                       nphi, 2.0 * M_PI / nphi);
+    const int gx = (plane + faceflux::THREADS - 1) / faceflux::THREADS;
+    const int chunks = (nr + faceflux::ROWS - 1) / faceflux::ROWS;
+    hipLaunchKernelGGL(faceflux::k_face_fluxes, dim3(gx * chunks), dim3(faceflux::THREADS), 0, s, phi, B, fr, ft, fp,
+                       t, nr, nth, nphi, 2.0 * M_PI / nphi, gx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_face_fluxes: ") + hipGetErrorString(e));
     return SPP_OK;
