@@ -64,28 +64,34 @@ def stage_model(nr, nth, nphi, parity, fused):
     }
 
 
-# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (the profiles/ summary named for that kernel and workload), scaled by
-# the same counters read over a device copy of known size.  Valid only for the
-# kernel sources it was taken with: if they have changed, it is withheld.
-TRAFFIC = {"kernel": "modal::k_modal", "grid": (550, 128, 256), "source_digest": "d349ed14b7fdcb2f",
-           "bytes_per_launch": (81366.97 * 2.0 + 140806.0) * 1024.0}
-TRAFFIC_SOURCES = ("modal.hip.h", "modal_layout.h", "radial.hip.h", "solve.hip")
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (the
+# profiles/ summaries named for each kernel and workload), scaled by the same
+# counters read over a device copy of known size (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0).  Each figure is valid only for the kernel sources it was
+# taken with: if they have changed, it is withheld.
+TRAFFIC = {
+    "modal::k_modal": {"grid": (550, 128, 256), "sources": ("modal.hip.h", "modal_layout.h", "radial.hip.h", "solve.hip"),
+                       "source_digest": "f6b9d8ac8badd61a",
+                       "bytes_per_launch": (81367.3 * 2.0 + 140806.0) * 1024.0},
+    "faceflux::k_face_fluxes": {"grid": (550, 128, 256), "sources": ("fluxes.hip.h", "solve.hip"),
+                                "source_digest": "5cf6879d624ba0c0",
+                                "bytes_per_launch": (74480.22 * 2.0 + 422573.38) * 1024.0},
+}
 
 
-def _kernel_source_digest():
+def _kernel_source_digest(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1806_06623_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, nr, nth, nphi):
-    t = TRAFFIC
-    if (t is None or kernel != t["kernel"] or (nr, nth, nphi) != tuple(t["grid"])
-            or _kernel_source_digest() != t["source_digest"]):
+    t = TRAFFIC.get(kernel)
+    if (t is None or t["bytes_per_launch"] is None or (nr, nth, nphi) != tuple(t["grid"])
+            or _kernel_source_digest(t["sources"]) != t["source_digest"]):
         return None
     return round(t["bytes_per_launch"], 0)
 
@@ -383,7 +389,8 @@ def main():
         face = {"ms": round(ms, 5), "alg_bytes": fbytes, "GBps": round(fbytes / (ms * 1e-3) / 1e9, 1),
                 "hbm_frac": round(fbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "note": "whole entry point: outer-shell boundary term (shell FFT, per-mode beta, inverse "
-                        "FFT) and the flux stencil; algorithmic bytes = Phi read once + three flux fields"}
+                        "FFT) and the flux stencil; algorithmic bytes = Phi read once + three flux fields",
+                "stencil_traffic": measured_traffic("faceflux::k_face_fluxes", nr, nth, nphi)}
         log(f"face fluxes: {ms * 1e3:.1f} us per call, {face['GBps']} GB/s")
         del fl
 
