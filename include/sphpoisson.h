@@ -172,8 +172,8 @@ spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double 
  *   phi_dev        device, [N_r][N_theta][N_phi] float64, read-only;
  *   fr/ft/fp_dev   device, same shape each, written;
  *   workspace_dev  device scratch of the plan's workspace_bytes (256-byte aligned).
- * All four fields 16-byte aligned and pairwise disjoint.  The call reads the
- * plan's uploaded tables and allocates nothing.
+ * All four fields 16-byte aligned, pairwise disjoint and disjoint from the
+ * workspace.  The call reads the plan's uploaded tables and allocates nothing.
  * Errors (synchronous, nothing enqueued): SPP_EINVAL (NULL, misaligned,
  * overlap), SPP_ESTATE (plan not uploaded), SPP_ENOTSUP (N_theta > 3840),
  * SPP_EDEVICE (launch failure).

@@ -649,12 +649,17 @@ extern "C" spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double*
     const size_t n = size_t(p->nr) * p->nth * p->nphi * sizeof(double);
     const char* b[4] = {reinterpret_cast<const char*>(phi_dev), reinterpret_cast<const char*>(fr_dev),
                         reinterpret_cast<const char*>(ft_dev), reinterpret_cast<const char*>(fp_dev)};
+    // the part of the workspace the call uses: two shells of N_theta N_phi doubles
+    const size_t wsn = 2 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
+    const char* wsb = static_cast<const char*>(workspace_dev);
     for (int x = 0; x < 4; ++x) {
         if (reinterpret_cast<uintptr_t>(b[x]) & 15)
             return spp_fail(SPP_EINVAL, "spp_face_fluxes: field pointers must be 16-byte aligned");
         for (int y = x + 1; y < 4; ++y)
             if (b[x] < b[y] + n && b[y] < b[x] + n)
                 return spp_fail(SPP_EINVAL, "spp_face_fluxes: phi and the three flux fields must not overlap");
+        if (b[x] < wsb + wsn && wsb < b[x] + n)
+            return spp_fail(SPP_EINVAL, "spp_face_fluxes: the workspace must not overlap phi or the flux fields");
     }
     return spp_launch_face_fluxes(p, phi_dev, fr_dev, ft_dev, fp_dev, workspace_dev, stream);
 }

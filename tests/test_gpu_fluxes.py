@@ -132,5 +132,6 @@ def test_argument_errors_enqueue_nothing():
     assert lib.spp_face_fluxes(plan._plan, ptr(phi), ptr(fr), ptr(ft), ptr(phi), ws, s) == -1  # alias of phi
     assert lib.spp_face_fluxes(plan._plan, vp(phi.data_ptr() + 8), ptr(fr), ptr(ft), ptr(fp), ws, s) == -1   # misaligned phi
     assert lib.spp_face_fluxes(plan._plan, ptr(phi), ptr(fr), ptr(ft), ptr(fp), vp(ws.value + 64), s) == -1   # misaligned workspace
+    assert lib.spp_face_fluxes(plan._plan, ptr(phi), ptr(fr), ptr(ft), ptr(fp), ptr(fp), s) == -1   # workspace on a flux field
     assert lib.spp_face_fluxes(plan._plan, ptr(phi), ptr(fr), ptr(ft), ptr(fp), ws, s) == 0
     torch.cuda.synchronize()
