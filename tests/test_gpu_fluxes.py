@@ -58,17 +58,19 @@ def test_fluxes_of_the_solution_gaussian_blob():
     _compare(c["name"], got, fluxes.face_fluxes(c["r_if"], c["th_if"], c["nphi"], phi))
 
 
-@pytest.mark.parametrize("nr,nth,nphi,seed,uniform_theta", [
-    (37, 6, 8, 1, True),      # rows not a multiple of the 16-row chunk, plane of 48 (< one block)
-    (2, 4, 4, 2, True),       # smallest grid of the fused path
-    (2, 2, 4, 3, True),       # smallest grid (staged path only: N_theta = 2)
-    (40, 24, 16, 4, False),   # non-uniform theta, plane of 384 (a block and a half)
-    (17, 128, 256, 5, True),  # full angular grid, one row past a chunk
-    (5, 3, 2048, 6, True),    # largest N_phi
+@pytest.mark.parametrize("nr,nth,nphi,seed,uniform_theta,r0", [
+    (37, 6, 8, 1, True, 0.0),      # rows not a multiple of the 8-row chunk, plane of 48 (< one block)
+    (2, 4, 4, 2, True, 0.0),       # smallest grid of the fused path
+    (2, 2, 4, 3, True, 0.0),       # smallest grid (staged path only: N_theta = 2)
+    (40, 24, 16, 4, False, 0.0),   # non-uniform theta, plane of 384 (a block and a half)
+    (17, 128, 256, 5, True, 0.0),  # full angular grid, one row past a chunk (XCD-ordered plane blocks)
+    (5, 3, 2048, 6, True, 0.0),    # largest N_phi
+    (12, 8, 16, 7, False, 2.0),    # inner boundary at r = 2 (zero-flux face, not stored)
+    (6, 200, 8, 8, True, 0.0),     # N_theta = 200: outer-term products over 7 partial 32-column blocks
 ])
-def test_fluxes_of_random_fields(nr, nth, nphi, seed, uniform_theta):
+def test_fluxes_of_random_fields(nr, nth, nphi, seed, uniform_theta, r0):
     rng = np.random.default_rng(seed)
-    r_if = np.concatenate(([0.0], np.cumsum(rng.uniform(0.3, 1.7, nr))))
+    r_if = np.concatenate(([r0], r0 + np.cumsum(rng.uniform(0.3, 1.7, nr))))
     if uniform_theta:
         th_if = synthetic.theta_interfaces(nth)
     else:
