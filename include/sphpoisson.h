@@ -155,8 +155,8 @@ spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double 
  * the sum over a cell's six faces of area x difference quotient; Sec. 3.2 for
  * the outer boundary face).  For Phi from spp_solve the six fluxes of every
  * cell add up to 4 pi G rho delta V to rounding (Gauss's law on the grid):
- * the building block of gravitational momentum and energy source terms in
- * conservative form (Sec. 1, Sec. 3.1).  Each flux is signed along its
+ * what a hydrodynamics code builds conservative gravity terms for its
+ * momentum and energy equations from (Sec. 1, Sec. 3.1).  Each flux is signed along its
  * increasing coordinate:
  *   fr_dev[i][j][k]  face i+1/2:  r_{i+1/2}^2 dmu_j dphi (Phi_{i+1} - Phi_i)/(r_{i+1} - r_i);
  *                    i = N_r - 1 is the outer boundary face, dmu_j dphi times
