@@ -137,3 +137,28 @@ def test_argument_errors_enqueue_nothing():
     assert lib.spp_face_fluxes(plan._plan, ptr(phi), ptr(fr), ptr(ft), ptr(fp), ptr(fp), s) == -1   # workspace on a flux field
     assert lib.spp_face_fluxes(plan._plan, ptr(phi), ptr(fr), ptr(ft), ptr(fp), ws, s) == 0
     torch.cuda.synchronize()
+
+
+def test_face_fluxes_replay_in_a_hip_graph():
+    """The call allocates nothing and records no memset, so a caller may
+    capture it: three replays of a captured call, with eager work on the
+    device between them, each equal bit for bit to the eager call."""
+    import paper_1806_06623_amd as spp
+    c = synthetic.stellar_case(nr=48, nth=32, nphi=64, seed=13)
+    plan = spp.Plan(c["r_if"], c["th_if"], c["nphi"])
+    phi = torch.from_numpy(np.random.default_rng(13).standard_normal((48, 32, 64))).to("cuda")
+    ref = [f.clone() for f in plan.face_fluxes(phi)]          # eager (also warms the launch caches)
+    out = tuple(torch.full_like(phi, float("nan")) for _ in range(3))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.face_fluxes(phi, out=out)
+    for rep in range(3):
+        for o in out:
+            o.fill_(float("nan"))
+        scratch = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        scratch.mul_(2.0)                                      # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(out, ref):
+            assert torch.equal(o, r), f"replay {rep}"
