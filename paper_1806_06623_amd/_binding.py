@@ -179,6 +179,18 @@ class Plan:
     def shape(self):
         return (self.nr, self.nth, self.nphi)
 
+    def _check_field(self, t, name):
+        import torch
+        if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous()
+                or tuple(t.shape) != self.shape or t.device != self.device):
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {self.shape} on {self.device}")
+
+    def _check_workspace(self, ws, need):
+        import torch
+        if (not isinstance(ws, torch.Tensor) or not ws.is_contiguous() or ws.device != self.device
+                or ws.numel() * ws.element_size() < need):
+            raise ValueError(f"workspace must be a contiguous tensor of at least {need} bytes on {self.device}")
+
     def new_workspace(self):
         import torch
         return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
@@ -191,7 +203,9 @@ class Plan:
             raise ValueError("rho must live on the plan's device")
         if out is None:
             out = torch.empty_like(rho)
+        self._check_field(out, "out")
         ws = self.workspace if workspace is None else workspace
+        self._check_workspace(ws, self.workspace_bytes)
         _check(lib.spp_solve(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
                              _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_solve")
         return out
@@ -208,7 +222,10 @@ class Plan:
         if out is None:
             out = tuple(torch.empty_like(phi) for _ in range(3))
         fr, ft, fp = out
+        for t, name in ((fr, "out[0]"), (ft, "out[1]"), (fp, "out[2]")):
+            self._check_field(t, name)
         ws = self.workspace if workspace is None else workspace
+        self._check_workspace(ws, self.workspace_bytes)
         _check(lib.spp_face_fluxes(self._plan, _vp(phi.data_ptr()), _vp(fr.data_ptr()), _vp(ft.data_ptr()),
                                    _vp(fp.data_ptr()), _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_face_fluxes")
         return fr, ft, fp
@@ -227,11 +244,13 @@ class Plan:
             raise ValueError(f"rho must be a contiguous float64 tensor of shape {self.shape}")
         if out is None:
             out = torch.empty_like(rho)
+        self._check_field(out, "out")
+        need = self.workspace_bytes_for(precision)
         if workspace is None:
-            need = self.workspace_bytes_for(precision)
             if getattr(self, "_mixed_ws", None) is None or self._mixed_ws.numel() < need:
                 self._mixed_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             workspace = self._mixed_ws
+        self._check_workspace(workspace, need)
         _check(lib.spp_solve_mixed(self._plan, precision_codes[precision], int(n_refine), _vp(rho.data_ptr()),
                                    _vp(out.data_ptr()), float(G), _vp(workspace.data_ptr()),
                                    _stream_ptr(stream)), "spp_solve_mixed")
@@ -243,6 +262,8 @@ class Plan:
         Returns the five stage durations in ms (forward FFT, forward
         projection, radial solves, inverse projection, inverse FFT).
         """
+        self._check_field(rho, "rho")
+        self._check_field(out, "out")
         st = np.zeros(5)
         _check(lib.spp_solve_profiled(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
                                       _vp(self.workspace.data_ptr()), _stream_ptr(stream),

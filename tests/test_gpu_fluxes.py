@@ -162,3 +162,27 @@ def test_face_fluxes_replay_in_a_hip_graph():
         torch.cuda.synchronize()
         for o, r in zip(out, ref):
             assert torch.equal(o, r), f"replay {rep}"
+
+
+def test_binding_rejects_wrong_buffers_before_launching():
+    """Output tensors and workspaces the caller passes are checked by the
+    binding (the C ABI sees plain pointers and cannot): wrong shape, dtype or
+    size raises ValueError and nothing is enqueued."""
+    import paper_1806_06623_amd as spp
+    plan = spp.Plan(np.array([0.0, 1.0, 2.0, 3.0]), synthetic.theta_interfaces(8), 16)
+    phi = torch.zeros(plan.shape, dtype=torch.float64, device="cuda")
+    good = tuple(torch.empty_like(phi) for _ in range(3))
+    small_ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        plan.face_fluxes(phi, out=(good[0], good[1], torch.empty(7, dtype=torch.float64, device="cuda")))
+    with pytest.raises(ValueError):
+        plan.face_fluxes(phi, out=(good[0], good[1], good[2].float()))
+    with pytest.raises(ValueError):
+        plan.face_fluxes(phi, workspace=small_ws)
+    with pytest.raises(ValueError):
+        plan.solve(phi, out=torch.empty((2, 8, 16), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.solve(phi, workspace=small_ws)
+    with pytest.raises(ValueError):
+        plan.solve_mixed(phi, workspace=small_ws)
+    torch.cuda.synchronize()
