@@ -305,8 +305,9 @@ class Batch:
             raise ValueError("plans, rhos, phis and Gs must have the same non-zero length")
         for p, x, y in zip(plans, rhos, phis):
             for t in (x, y):
-                if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != p.shape:
-                    raise ValueError(f"tensors must be contiguous float64 of shape {p.shape}")
+                if (t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != p.shape
+                        or t.device != p.device):
+                    raise ValueError(f"tensors must be contiguous float64 of shape {p.shape} on {p.device}")
         self._keep = (list(plans), list(rhos), list(phis))
         self.n = n
         self._plans = (_vp * n)(*[p._plan for p in plans])
@@ -357,6 +358,11 @@ class Server:
         return t.value
 
     def submit(self, plan_index, rho, phi, G=1.0, request_id=0, not_before=0.0):
+        if not 0 <= int(plan_index) < len(self.plans):
+            raise ValueError(f"plan_index must be in [0, {len(self.plans)})")
+        plan = self.plans[int(plan_index)]
+        plan._check_field(rho, "rho")
+        plan._check_field(phi, "phi")
         req = _Request(int(plan_index), _vp(rho.data_ptr()), _vp(phi.data_ptr()), float(G), int(request_id))
         _check(lib.spp_server_submit(self._s, ctypes.byref(req), float(not_before)), "spp_server_submit")
         self._live[int(request_id)] = (rho, phi)
