@@ -63,12 +63,15 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(
         if constexpr (FOLD) {
 #pragma unroll
             for (int u = 0; u < PER / 2; ++u) {
+                // 32-bit pair arithmetic: the folded layout serves the grids of
+                // the fused per-mode kernel (N_r N_theta <= 576 x 128), and a
+                // 64-bit division per load would hold the loads back
                 const int e = threadIdx.x + TH * u;
-                size_t P = size_t(blk) * PB + e / N2;
-                P = P < npairs ? P : npairs - 1;
-                const int i = int(P / h), k = int(P - size_t(i) * h);
-                pre[2 * u] = src[(size_t(i) * nth + k) * N2 + e % N2];
-                pre[2 * u + 1] = src[(size_t(i) * nth + nth - 1 - k) * N2 + e % N2];
+                unsigned P = unsigned(blk) * PB + unsigned(e / N2);
+                P = P < unsigned(npairs) ? P : unsigned(npairs) - 1;
+                const unsigned i = P / unsigned(h), k = P - i * unsigned(h);
+                pre[2 * u] = src[size_t(i * unsigned(nth) + k) * N2 + e % N2];
+                pre[2 * u + 1] = src[size_t(i * unsigned(nth) + unsigned(nth) - 1 - k) * N2 + e % N2];
             }
         } else {
             const size_t base = size_t(blk) * JB * N2 + threadIdx.x;
@@ -111,10 +114,10 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(
         bool valid;
         size_t oline;
         if constexpr (FOLD) {
-            const size_t P = size_t(blk) * PB + (l % PB);
-            valid = P < npairs;
-            const int i = int(P / h), k = int(P - size_t(i) * h);
-            oline = size_t(i) * nth + (l / PB) * h + k;
+            const unsigned P = unsigned(blk) * PB + unsigned(l % PB);
+            valid = P < unsigned(npairs);
+            const unsigned i = valid ? P / unsigned(h) : 0, k = P - i * unsigned(h);
+            oline = size_t(i * unsigned(nth) + unsigned(l / PB) * unsigned(h) + k);
         } else {
             oline = size_t(blk) * JB + l;
             valid = oline < size_t(nlines);
@@ -180,10 +183,10 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
     auto prefetch = [&](int blk) {
         size_t L;
         if constexpr (FOLD) {
-            size_t P = size_t(blk) * PB + (l % PB);
-            P = P < npairs ? P : npairs - 1;
-            const int i = int(P / h), k = int(P - size_t(i) * h);
-            L = size_t(i) * nth + (l / PB) * h + k;
+            unsigned P = unsigned(blk) * PB + unsigned(l % PB);
+            P = P < unsigned(npairs) ? P : unsigned(npairs) - 1;
+            const unsigned i = P / unsigned(h), k = P - i * unsigned(h);
+            L = size_t(i * unsigned(nth) + unsigned(l / PB) * unsigned(h) + k);
         } else {
             L = size_t(min(blk * JB + l, nlines - 1));
         }
@@ -235,9 +238,9 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
 #pragma unroll
             for (int u = 0; u < PER / 2; ++u) {
                 const int e = threadIdx.x + TH * u;
-                const size_t P = size_t(blk) * PB + e / N2;
-                if (P < npairs) {
-                    const int i = int(P / h), k = int(P - size_t(i) * h);
+                const unsigned P = unsigned(blk) * PB + unsigned(e / N2);
+                if (P < unsigned(npairs)) {
+                    const unsigned i = P / unsigned(h), k = P - i * unsigned(h);
                     const c64 ve = lds[(e / N2) * LS + pidx(e % N2)];
                     const c64 vo = lds[(PB + e / N2) * LS + pidx(e % N2)];
                     dst[(size_t(i) * nth + k) * N2 + e % N2] = double2{ve.x + vo.x, -(ve.y + vo.y)};
