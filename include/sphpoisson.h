@@ -74,6 +74,11 @@ typedef struct {
     double* phi_dev;         /* device, same shape, written                       */
     double G;
     long long request_id;    /* caller's tag, echoed in the completion            */
+    void* ready_event;       /* hipEvent_t recorded by the caller after the work
+                                that writes rho (on any stream); the solve's slot
+                                stream waits for it.  NULL: rho is already
+                                complete on the device at submission.  The event
+                                must stay valid until the completion is polled. */
 } spp_request;
 
 /* Completion record; times in seconds on the server's steady clock. */
@@ -281,7 +286,9 @@ spp_status spp_solve_batched(int n, const spp_plan* plans, const double* const* 
  *   spp_server_destroy: drops queued requests, waits for running ones.
  * Each request runs exactly the kernels of spp_solve, so its result is
  * bitwise the same alone and in any mix.  rho/phi buffers must stay valid
- * until the request's completion has been polled.
+ * until the request's completion has been polled.  The slot streams do not
+ * wait on the caller's streams: rho must be complete at submission, or the
+ * request names a ready_event to wait for.
  */
 spp_status spp_server_create(int n_plans, const spp_plan* plans, void* pool_dev, size_t pool_bytes, int n_slots,
                              spp_server* out);
@@ -330,6 +337,17 @@ spp_status spp_plan_parity_split(spp_plan p, int* on);
  */
 spp_status spp_plan_set_path(spp_plan p, spp_path path);
 spp_status spp_plan_get_path(spp_plan p, spp_path* path);
+
+/*
+ * Names of the kernels one FP64 solve of this plan launches, in launch order,
+ * separated by semicolons (e.g. "k_rfft_fwd<256,fold>;modal::k_modal<4,3>;..."), for
+ * tests and diagnostics; they follow the current path (spp_plan_set_path).
+ *   buf     host, len bytes; receives the NUL-terminated list, truncated to
+ *           len - 1 characters (buf may be NULL when len == 0);
+ *   needed  host, may be NULL; receives the length including the NUL.
+ * Errors: SPP_EINVAL (NULL plan).
+ */
+spp_status spp_plan_kernels(spp_plan p, char* buf, size_t len, size_t* needed);
 
 /* Grid sizes of a plan (any pointer may be NULL). */
 spp_status spp_plan_shape(spp_plan p, int* nr, int* nth, int* nphi);

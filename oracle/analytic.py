@@ -60,12 +60,21 @@ def ellipsoid_potential(x, y, z, a, b, c, rho0=1.0, G=1.0):
     x, y, z = np.broadcast_arrays(x, y, z)
     out = x * x / a2 + y * y / b2 + z * z / c2 > 1.0
     xo, yo, zo = x[out], y[out], z[out]
-    # the left side decreases monotonically in u; Newton from u = r^2 - a^2
+    # the left side decreases monotonically in u; Newton from u = r^2 - a^2,
+    # until the steps stop shrinking at rounding level (two more steps after
+    # the largest relative step falls below 1e-13)
     uo = np.maximum(xo * xo + yo * yo + zo * zo - a2, 0.0)
+    extra = 2
     for _ in range(60):
         f = xo * xo / (a2 + uo) + yo * yo / (b2 + uo) + zo * zo / (c2 + uo) - 1.0
         df = -(xo * xo / (a2 + uo) ** 2 + yo * yo / (b2 + uo) ** 2 + zo * zo / (c2 + uo) ** 2)
-        uo = np.maximum(uo - f / df, 0.0)
+        un = np.maximum(uo - f / df, 0.0)
+        step = float(np.max(np.abs(un - uo) / (1.0 + un))) if un.size else 0.0
+        uo = un
+        if step < 1e-13:
+            extra -= 1
+            if extra < 0:
+                break
     u[out] = uo
     A = 2.0 / 3.0 * elliprd(b2 + u, c2 + u, a2 + u)
     B = 2.0 / 3.0 * elliprd(a2 + u, c2 + u, b2 + u)

@@ -18,7 +18,14 @@ whole (theta, phi) shell:
 with r_o the outer interface and r_N the outermost cell centre.  A is
 self-adjoint in the solid-angle-weighted inner product, so P(A) is formed
 from the symmetric eigendecomposition of W^1/2 A W^-1/2, W = diag(cell solid
-angles).  The unknown ordering is C order over (i, j, k).
+angles).  Under the regular inner condition (r_i = r_{1/2} > 0) the inner face
+is built the same way:
+
+    face derivative along +r = (1/r_i) Q(A) Phi_shell,
+    Q(lambda) = p' (r_i / r_1)^p',   p' = (-1 + sqrt(1 - 4 lambda))/2,
+
+with r_1 the innermost cell centre.  The unknown ordering is C order over
+(i, j, k).
 """
 import numpy as np
 
@@ -67,29 +74,60 @@ def shell_angular_operator(th_if, nphi):
     return A, omega
 
 
-def outer_face_operator(r_if, th_if, nphi):
-    """Matrix P(A) of the outer boundary condition (see module docstring)."""
-    r_if = np.asarray(r_if, dtype=np.float64)
-    ro = r_if[-1]
-    rn = 0.5 * (r_if[-2] + r_if[-1])
+def _shell_matrix_function(th_if, nphi, fn):
+    """fn(A) for the unit-sphere angular operator A of the shell."""
     A, omega = shell_angular_operator(th_if, nphi)
     sw = np.sqrt(omega)
     Asym = sw[:, None] * A / sw[None, :]
     Asym = 0.5 * (Asym + Asym.T)
     lam, Q = np.linalg.eigh(Asym)
-    p = 0.5 * (1.0 + np.sqrt(1.0 - 4.0 * lam))
-    Psym = (Q * (p * (ro / rn) ** (-p))) @ Q.T
+    Psym = (Q * fn(lam)) @ Q.T
     return Psym / sw[:, None] * sw[None, :]
 
 
-def assemble(r_if, th_if, nphi):
-    """Dense L of size (nr*nth*nphi)^2 from the flux form (Sec. 3.1)."""
+def outer_face_operator(r_if, th_if, nphi):
+    """Matrix P(A) of the outer boundary condition (see module docstring)."""
+    r_if = np.asarray(r_if, dtype=np.float64)
+    ro = r_if[-1]
+    rn = 0.5 * (r_if[-2] + r_if[-1])
+
+    def P(lam):
+        p = 0.5 * (1.0 + np.sqrt(1.0 - 4.0 * lam))
+        return p * (ro / rn) ** (-p)
+    return _shell_matrix_function(th_if, nphi, P)
+
+
+def inner_face_operator(r_if, th_if, nphi):
+    """Matrix Q(A) of the regular inner condition (see module docstring)."""
+    r_if = np.asarray(r_if, dtype=np.float64)
+    ri = r_if[0]
+    r1 = 0.5 * (r_if[0] + r_if[1])
+
+    def Q(lam):
+        pp = 0.5 * (-1.0 + np.sqrt(np.maximum(1.0 - 4.0 * lam, 1.0)))
+        return pp * (ri / r1) ** pp
+    return _shell_matrix_function(th_if, nphi, Q)
+
+
+def assemble_parts(r_if, th_if, nphi, inner="zero_flux"):
+    """Dense L = L_local + L_boundary (Sec. 3.1), each (nr*nth*nphi)^2.
+
+    L_local holds the face couplings between neighbouring cells (the local
+    stencil of the flux form); L_boundary the outer boundary face of the
+    outermost shell, which couples every cell of that shell to the whole
+    shell through P(A), and, for inner="regular" with r_{1/2} > 0, the inner
+    face of the innermost shell through Q(A) (see the module docstring).
+    """
+    if inner not in ("zero_flux", "regular"):
+        raise ValueError("inner must be 'zero_flux' or 'regular'")
     r_if, th_if, r, th, dphi = _cells(r_if, th_if, nphi)
     nr, nth = r.size, th.size
     n = nr * nth * nphi
     L = np.zeros((n, n))
+    Lo = np.zeros((n, n))
     idx = lambda i, j, k: (i * nth + j) * nphi + (k % nphi)
     P = outer_face_operator(r_if, th_if, nphi)
+    Q = inner_face_operator(r_if, th_if, nphi) if inner == "regular" and r_if[0] > 0.0 else None
     for i in range(nr):
         rm, rp = r_if[i], r_if[i + 1]
         for j in range(nth):
@@ -126,13 +164,25 @@ def assemble(r_if, th_if, nphi):
                     area = rp ** 2 * (np.cos(tm) - np.cos(tp)) * dphi
                     row = (j * nphi + k)
                     base = idx(i, 0, 0)
-                    L[c, base:base + nth * nphi] -= area / rp * P[row] / dV
-    return L
+                    Lo[c, base:base + nth * nphi] -= area / rp * P[row] / dV
+                if i == 0 and Q is not None:
+                    # inner face: flux along +r = area ri^2 dOmega_jk times
+                    # (1/ri) Q(A) Phi_shell; it enters cell 0, so -flux / dV
+                    area = rm ** 2 * (np.cos(tm) - np.cos(tp)) * dphi
+                    row = (j * nphi + k)
+                    Lo[c, 0:nth * nphi] -= area / rm * Q[row] / dV
+    return L, Lo
 
 
-def solve(r_if, th_if, nphi, rho, G=1.0):
+def assemble(r_if, th_if, nphi, inner="zero_flux"):
+    """Dense L of size (nr*nth*nphi)^2 from the flux form (Sec. 3.1)."""
+    L, Lo = assemble_parts(r_if, th_if, nphi, inner)
+    return L + Lo
+
+
+def solve(r_if, th_if, nphi, rho, G=1.0, inner="zero_flux"):
     """Phi = L^-1 (4 pi G rho) by a dense LU solve."""
     rho = np.asarray(rho, dtype=np.float64)
-    L = assemble(r_if, th_if, nphi)
+    L = assemble(r_if, th_if, nphi, inner)
     s = 4.0 * np.pi * G * rho.reshape(-1)
     return np.linalg.solve(L, s).reshape(rho.shape)

@@ -28,7 +28,12 @@ Readings of the paper's text used here:
   equation drops the f after lambda_Omega);
 * the outer condition uses the value f_N in the outermost zone, extrapolated
   to the outer face with the decay law, and the discrete lambda_Omega;
-* the inner radial face has zero flux (zero area when r_{1/2} = 0).
+* the inner radial face (the paper is silent on it): zero area when
+  r_{1/2} = 0; otherwise either zero flux, or -- the "regular" condition --
+  the decay law's counterpart for the source-free region r < r_{1/2}: each
+  angular mode is the solution f ~ r^p', p' = (-1 + sqrt(1 - 4 lambda))/2, that
+  stays finite at the centre, extrapolated from the innermost zone to the
+  face.  Both agree for lambda = 0 (p' = 0).
 """
 import numpy as np
 from scipy.linalg import eigh_tridiagonal, solve_banded
@@ -55,20 +60,24 @@ def theta_operator(geom, lam_phi):
     return diag, off
 
 
-def theta_eigensystem(geom, m):
+def theta_eigensystem(geom, m, driver="stev"):
     """(lambda_Omega[l], H[j, l]) for azimuthal mode m (Sec. 3.2).
 
     Solves K H = lambda D H through the symmetric tridiagonal matrix
     D^-1/2 K D^-1/2 (scipy's eigh_tridiagonal with LAPACK's implicit QL/QR
     driver 'stev', whose eigenvectors are orthonormal to rounding), then
     H = D^-1/2 V, which makes H^T D H = I.  For m = 0 the null pair is exact
-    (see below).
+    (see below).  ``driver='stemr'`` (LAPACK's MRRR) is a second, independent
+    FP64 eigensolver: the spread between the two measures how well FP64
+    determines the solution on a given grid (eigenvalues come with an
+    absolute error near eps |K|, a relative one near eps |K| / |lambda| on
+    the small eigenvalues that dominate Phi).
     """
     lam_phi = phi_eigenvalues(geom["nphi"])[m]
     diag, off = theta_operator(geom, lam_phi)
     dmu = geom["dmu"]
     w = 1.0 / np.sqrt(dmu)
-    lam, vec = eigh_tridiagonal(diag * w * w, off * w[:-1] * w[1:], lapack_driver="stev")
+    lam, vec = eigh_tridiagonal(diag * w * w, off * w[:-1] * w[1:], lapack_driver=driver)
     H = w[:, None] * vec
     if m == 0:
         # No flux crosses the poles (Sec. 3.1), so for m = 0 every row of K
@@ -102,16 +111,38 @@ def outer_beta(geom, lam):
     return p * ro * (ro / rn) ** (-p)
 
 
-def radial_banded(geom, lam):
+INNER_CONDITIONS = ("zero_flux", "regular")
+
+
+def inner_gamma(geom, lam, inner="zero_flux"):
+    """gamma(lambda) with (face flux)/(dmu dphi) = gamma f_1 at the inner face.
+
+    Zero for the zero-flux condition and for r_{1/2} = 0 (the face has no
+    area).  For the regular condition, with p' = (-1 + sqrt(1 - 4 lambda))/2
+    the derivative at r_{1/2} is p' f_1 (r_{1/2}/r_1)^p' / r_{1/2}; times the
+    face area r_{1/2}^2 this is gamma f_1, gamma = p' r_{1/2} (r_{1/2}/r_1)^p'.
+    """
+    if inner not in INNER_CONDITIONS:
+        raise ValueError(f"inner condition must be one of {INNER_CONDITIONS}")
+    lam = np.asarray(lam, dtype=np.float64)
+    ri, r1 = geom["r_if"][0], geom["r"][0]
+    if inner == "zero_flux" or ri == 0.0:
+        return np.zeros_like(lam)
+    pp = 0.5 * (-1.0 + np.sqrt(1.0 - 4.0 * lam))
+    return pp * ri * (ri / r1) ** pp
+
+
+def radial_banded(geom, lam, inner="zero_flux"):
     """The radial operator Delta_r + R_i lambda as a (3, nr) banded matrix.
 
     Row i: a_i f_{i-1} + b_i f_i + c_i f_{i+1} with a_i = alpha_{i-1}/V_i,
     c_i = alpha_i/V_i, b_i = -(alpha_{i-1} + alpha_i)/V_i + R_i lambda, where
-    alpha_{-1} = 0 (inner face) and, on the outermost row, alpha_{N} is
-    replaced by beta(lambda) and c is absent.
+    on the innermost row alpha_{-1} is replaced by gamma(lambda) (zero for the
+    zero-flux condition) and a is absent, and on the outermost row alpha_{N}
+    is replaced by beta(lambda) and c is absent.
     """
     nr, V, R, al = geom["nr"], geom["V"], geom["R"], geom["alpha"]
-    lower = np.concatenate(([0.0], al))       # alpha_{i-1}, i=0..nr-1
+    lower = np.concatenate(([inner_gamma(geom, lam, inner)], al))   # alpha_{i-1} / gamma
     upper = np.concatenate((al, [outer_beta(geom, lam)]))   # alpha_i / beta
     ab = np.zeros((3, nr))
     ab[0, 1:] = al / V[:-1]                   # super-diagonal c_i, i = 0..nr-2
@@ -127,10 +158,11 @@ class Plan:
     (Sec. 3.2); ``solve`` then repeats steps 1-7 for any source.
     """
 
-    def __init__(self, r_if, th_if, nphi):
+    def __init__(self, r_if, th_if, nphi, driver="stev", inner="zero_flux"):
         self.geom = grid_geometry(r_if, th_if, nphi)
         self.nphi = nphi
-        self.modes = [theta_eigensystem(self.geom, m) for m in range(nphi // 2 + 1)]
+        self.inner = inner
+        self.modes = [theta_eigensystem(self.geom, m, driver) for m in range(nphi // 2 + 1)]
 
     def forward_fft(self, s):
         """s~_{ijm}, m = 0..nphi//2, normalised for synthesis without 1/N."""
@@ -150,7 +182,7 @@ class Plan:
             f = np.empty_like(sh)
             for l in range(lam.size):
                 rhs = np.stack([sh[l].real, sh[l].imag], axis=1)
-                sol = solve_banded((1, 1), radial_banded(geom, lam[l]), rhs)
+                sol = solve_banded((1, 1), radial_banded(geom, lam[l], self.inner), rhs)
                 f[l] = sol[:, 0] + 1j * sol[:, 1]
             g[:, :, m] = (H @ f).T
         return g
@@ -161,6 +193,6 @@ class Plan:
         return self.inverse_fft(self.solve_modes(self.forward_fft(s)))
 
 
-def solve(r_if, th_if, nphi, rho, G=1.0):
+def solve(r_if, th_if, nphi, rho, G=1.0, driver="stev", inner="zero_flux"):
     """One-shot convenience wrapper: Plan(r_if, th_if, nphi).solve(rho, G)."""
-    return Plan(r_if, th_if, nphi).solve(rho, G)
+    return Plan(r_if, th_if, nphi, driver, inner).solve(rho, G)

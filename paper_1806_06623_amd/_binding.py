@@ -60,7 +60,7 @@ lib.spp_solve_batched.restype = _c_int
 
 class _Request(ctypes.Structure):
     _fields_ = [("plan_index", _c_int), ("rho_dev", _vp), ("phi_dev", _vp), ("G", _c_double),
-                ("request_id", ctypes.c_longlong)]
+                ("request_id", ctypes.c_longlong), ("ready_event", _vp)]
 
 
 class _Completion(ctypes.Structure):
@@ -88,6 +88,8 @@ lib.spp_plan_get_path.argtypes = [_vp, ctypes.POINTER(_c_int)]
 lib.spp_plan_get_path.restype = _c_int
 lib.spp_theta_eigensystem.argtypes = [_vp, _c_int, _dp, _dp]
 lib.spp_theta_eigensystem.restype = _c_int
+lib.spp_plan_kernels.argtypes = [_vp, ctypes.c_char_p, _c_size_t, ctypes.POINTER(_c_size_t)]
+lib.spp_plan_kernels.restype = _c_int
 lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
 lib.spp_plan_shape.restype = _c_int
 lib.spp_last_error.argtypes = []
@@ -176,6 +178,15 @@ class Plan:
         return bool(on.value)
 
     @property
+    def kernels(self):
+        """Kernels one FP64 solve launches, in order (see spp_plan_kernels)."""
+        need = _c_size_t()
+        _check(lib.spp_plan_kernels(self._plan, None, 0, ctypes.byref(need)), "spp_plan_kernels")
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.spp_plan_kernels(self._plan, buf, need.value, None), "spp_plan_kernels")
+        return buf.value.decode().split(";")
+
+    @property
     def shape(self):
         return (self.nr, self.nth, self.nphi)
 
@@ -240,8 +251,7 @@ class Plan:
                     stream=None):
         """Mixed-precision solve with FP64 refinement (see spp_solve_mixed)."""
         import torch
-        if rho.dtype != torch.float64 or not rho.is_contiguous() or tuple(rho.shape) != self.shape:
-            raise ValueError(f"rho must be a contiguous float64 tensor of shape {self.shape}")
+        self._check_field(rho, "rho")
         if out is None:
             out = torch.empty_like(rho)
         self._check_field(out, "out")
@@ -350,22 +360,34 @@ class Server:
         _check(lib.spp_server_create(len(self.plans), arr, _vp(self.pool.data_ptr()), self.pool.numel(),
                                      int(n_slots), ctypes.byref(s)), "spp_server_create")
         self._s = s
+        # requests in flight, keyed by the binding's own sequence number (the
+        # tag the library sees): caller tags may repeat
         self._live = {}
+        self._seq = 0
 
     def now(self):
         t = _c_double()
         _check(lib.spp_server_now(self._s, ctypes.byref(t)), "spp_server_now")
         return t.value
 
-    def submit(self, plan_index, rho, phi, G=1.0, request_id=0, not_before=0.0):
+    def submit(self, plan_index, rho, phi, G=1.0, request_id=0, not_before=0.0, stream=None):
+        """Queue one solve.  An event recorded on `stream` (default: the
+        current torch stream) after the work queued so far makes the slot
+        stream wait until rho is written."""
+        import torch
         if not 0 <= int(plan_index) < len(self.plans):
             raise ValueError(f"plan_index must be in [0, {len(self.plans)})")
         plan = self.plans[int(plan_index)]
         plan._check_field(rho, "rho")
         plan._check_field(phi, "phi")
-        req = _Request(int(plan_index), _vp(rho.data_ptr()), _vp(phi.data_ptr()), float(G), int(request_id))
+        ready = torch.cuda.Event()
+        ready.record(stream if stream is not None else torch.cuda.current_stream(plan.device))
+        seq = self._seq
+        self._seq += 1
+        req = _Request(int(plan_index), _vp(rho.data_ptr()), _vp(phi.data_ptr()), float(G), seq,
+                       _vp(ready.cuda_event))
         _check(lib.spp_server_submit(self._s, ctypes.byref(req), float(not_before)), "spp_server_submit")
-        self._live[int(request_id)] = (rho, phi)
+        self._live[seq] = (int(request_id), rho, phi, ready)
 
     def poll(self, max_out=4096):
         buf = (_Completion * max_out)()
@@ -373,8 +395,8 @@ class Server:
         _check(lib.spp_server_poll(self._s, buf, max_out, ctypes.byref(n)), "spp_server_poll")
         out = []
         for c in buf[:n.value]:
-            self._live.pop(int(c.request_id), None)
-            out.append(dict(request_id=c.request_id, plan_index=c.plan_index, t_arrival=c.t_arrival,
+            tag = self._live.pop(int(c.request_id), (int(c.request_id),))[0]
+            out.append(dict(request_id=tag, plan_index=c.plan_index, t_arrival=c.t_arrival,
                             t_admit=c.t_admit, t_done=c.t_done, status=c.status))
         return out
 

@@ -33,14 +33,17 @@ def _run(cmd):
 
 
 def build(verbose=True):
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJDIR, exist_ok=True)
-    objs = []
+    jobs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(OBJDIR, src.replace(".", "_") + ".o")
-        lang = ["-x", "hip"] + DEVICE if src.endswith(".hip") else ["-x", "hip"] + DEVICE
-        _run([HIPCC] + COMMON + lang + ["-c", path, "-o", obj])
-        objs.append(obj)
+        # every source is compiled as HIP for gfx950 (host code included)
+        jobs.append(([HIPCC] + COMMON + ["-x", "hip"] + DEVICE + ["-c", path, "-o", obj], obj))
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda j: _run(j[0]), jobs))
+    objs = [o for _, o in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lpthread"])
     os.replace(tmp, LIB)

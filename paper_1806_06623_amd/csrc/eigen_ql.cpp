@@ -1,6 +1,7 @@
 // Symmetric tridiagonal eigensolver: QL iteration with implicit Wilkinson
-// shifts (Bowdler, Martin, Reinsch & Wilkinson, Numer. Math. 11 (1968) 293,
-// "The QR and QL algorithms for symmetric matrices").  The rotations are
+// shifts (Dubrulle, Martin & Wilkinson, Numer. Math. 12 (1968) 377, "The
+// implicit QL algorithm"; the explicit-shift form is Bowdler, Martin, Reinsch
+// & Wilkinson, Numer. Math. 11 (1968) 293).  The rotations are
 // accumulated into an identity matrix, so the eigenvectors come out
 // orthonormal to rounding, which the projections rely on (H^-1 = H^T D).
 #include <algorithm>

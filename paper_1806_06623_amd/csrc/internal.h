@@ -87,6 +87,9 @@ spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double
 spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* stream, int* chosen_rm);
 void spp_prewarm_launch_caches(const spp_plan_s* p);
 
+// Kernels of an FP64 solve of this plan, separated by semicolons (solve.hip).
+std::string spp_describe_solve(const spp_plan_s* p);
+
 // Argument checks shared by the solve entry points (plan.cpp).
 spp_status spp_validate_solve(const char* who, const spp_plan_s* p, const double* rho_dev, const double* phi_dev,
                               double G, const void* workspace_dev);
@@ -102,8 +105,19 @@ inline bool spp_plan_fused(const spp_plan_s* p) { return p->fused_ok && p->path.
 
 constexpr size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Workspace bytes after the two fields of an FP64 solve that the fused
+// Workspace bytes after the spectral field of a fused FP64 solve that the
 // per-mode kernel uses as the sink of its stores of padding rows and columns:
 // one double per thread of its workgroup, shared by all its workgroups
 // (nothing reads them).
 constexpr size_t spp_modal_sink_bytes = spp_align256(size_t(modalimg::NW) * 64 * sizeof(double));
+
+// Workspace bytes of one FP64 solve on the fused path (one spectral field,
+// transformed in place, then the store sink) or on the staged path (two
+// fields); either also holds the two shells of spp_face_fluxes.
+inline size_t spp_path_workspace_bytes(const spp_plan_s* p, bool fused)
+{
+    const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
+    const size_t shells = 2 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
+    const size_t need = (fused && p->fused_ok) ? field + spp_modal_sink_bytes : 2 * field;
+    return need > shells ? need : shells;
+}

@@ -487,9 +487,9 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.Sj = take(p->Sj.size());
         L.lamphi = take(p->lamphi.size());
         L.total = off;
-        const size_t field = spp_align256(size_t(nr) * nth * nphi * sizeof(double));
-        // two fields; the fused per-mode kernel also needs its store sink
-        p->workspace_bytes = 2 * field + (p->fused_ok ? spp_modal_sink_bytes : 0);
+        // the larger of what either path needs (spp_plan_set_path may switch
+        // paths after the caller has sized its workspace)
+        p->workspace_bytes = std::max(spp_path_workspace_bytes(p, true), spp_path_workspace_bytes(p, false));
     } catch (const std::bad_alloc&) {
         delete p;
         return spp_fail(SPP_ENOMEM, "spp_plan_create: out of host memory");
@@ -535,6 +535,19 @@ extern "C" spp_status spp_plan_get_path(spp_plan p, spp_path* path)
 {
     if (!p || !path) return spp_fail(SPP_EINVAL, "spp_plan_get_path: NULL pointer");
     *path = spp_plan_fused(p) ? SPP_PATH_FUSED : SPP_PATH_STAGED;
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_plan_kernels(spp_plan p, char* buf, size_t len, size_t* needed)
+{
+    if (!p) return spp_fail(SPP_EINVAL, "spp_plan_kernels: NULL plan");
+    const std::string d = spp_describe_solve(p);
+    if (needed) *needed = d.size() + 1;
+    if (buf && len > 0) {
+        const size_t n = std::min(len - 1, d.size());
+        std::memcpy(buf, d.data(), n);
+        buf[n] = '\0';
+    }
     return SPP_OK;
 }
 

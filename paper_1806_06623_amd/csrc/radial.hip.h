@@ -51,9 +51,10 @@ struct RowCoef {
 
 // 1/w from the hardware reciprocal estimate y0 (relative error below 2^-24
 // on gfx950) and its residual e = 1 - w y0:  1/w = y0 / (1 - e)
-// = y0 (1 + e + e^2) + O(e^3 y0), and e^3 < 2^-72 lies far below the last
-// bit of float64 (the result is the correctly rounded reciprocal).  One
-// fused multiply-add fewer than two Newton steps.
+// = y0 (1 + e + e^2) + O(e^3 y0).  The truncation term e^3 < 2^-72 lies far
+// below the last bit of float64, so the error is that of the three rounded
+// operations, within about one ulp (not always the correctly rounded
+// reciprocal).  One fused multiply-add fewer than two Newton steps.
 __device__ __forceinline__ double recip(double w)
 {
     const double y = __builtin_amdgcn_rcp(w);

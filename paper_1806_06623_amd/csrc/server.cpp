@@ -147,17 +147,26 @@ void spp_server_s::run()
                 if (!free_slot) break;
                 const Pending job = queue.front();
                 const spp_plan_s* p = plans[job.req.plan_index];
+                // the workspace of the plan's current path (the fused path needs
+                // one spectral field, the staged path two)
+                const size_t need = spp_align256(spp_path_workspace_bytes(p, spp_plan_fused(p)));
                 size_t off = 0;
-                if (!alloc.alloc(spp_align256(p->workspace_bytes), &off)) break;   // wait for memory
+                if (!alloc.alloc(need, &off)) break;   // wait for memory
                 queue.pop_front();
                 free_slot->busy = true;
                 free_slot->job = job;
                 free_slot->ws_off = off;
-                free_slot->ws_bytes = spp_align256(p->workspace_bytes);
+                free_slot->ws_bytes = need;
                 free_slot->admitted = t;
                 lock.unlock();
-                spp_status st = spp_launch_solve_f64(p, job.req.rho_dev, job.req.phi_dev, job.req.G, pool + off,
-                                                     free_slot->stream);
+                spp_status st = SPP_OK;
+                if (job.req.ready_event &&
+                    hipStreamWaitEvent(free_slot->stream, static_cast<hipEvent_t>(job.req.ready_event), 0) !=
+                        hipSuccess)
+                    st = spp_fail(SPP_EDEVICE, "spp_server: hipStreamWaitEvent on the request's ready_event failed");
+                if (st == SPP_OK)
+                    st = spp_launch_solve_f64(p, job.req.rho_dev, job.req.phi_dev, job.req.G, pool + off,
+                                              free_slot->stream);
                 if (st == SPP_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess)
                     st = SPP_EDEVICE;
                 lock.lock();
@@ -236,7 +245,7 @@ extern "C" spp_status spp_server_submit(spp_server s, const spp_request* req, do
     const spp_plan_s* p = s->plans[req->plan_index];
     const spp_status st = spp_validate_solve("spp_server_submit", p, req->rho_dev, req->phi_dev, req->G, s->pool);
     if (st != SPP_OK) return st;
-    if (spp_align256(p->workspace_bytes) > s->pool_bytes)
+    if (spp_align256(spp_path_workspace_bytes(p, spp_plan_fused(p))) > s->pool_bytes)
         return spp_fail(SPP_ENOMEM, "spp_server_submit: request larger than the memory pool");
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) return spp_fail(SPP_ESTATE, "spp_server_submit: server is shutting down");

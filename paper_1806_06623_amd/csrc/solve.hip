@@ -421,7 +421,7 @@ std::vector<int> proj_rm_candidates(int rn)
 {
     switch (rn) {
     case 8: return {1, 2};
-    case 4: return {1, 2, 4};
+    case 4: return {1, 2};   // RM = 4 spills at this tile width
     default: return {2, 4};
     }
 }
@@ -450,7 +450,7 @@ bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, i
     if (rn == 8) {
         if (rm == 2) SPP_PROJ(8, 2); else SPP_PROJ(8, 1);
     } else if (rn == 4) {
-        if (rm == 1) SPP_PROJ(4, 1); else if (rm == 4) SPP_PROJ(4, 4); else SPP_PROJ(4, 2);
+        if (rm == 1) SPP_PROJ(4, 1); else SPP_PROJ(4, 2);
     } else if (rn == 2) {
         if (rm == 2) SPP_PROJ(2, 2); else SPP_PROJ(2, 4);
     } else {
@@ -496,40 +496,56 @@ bool launch_proj(const double* A, const double* B, double* C, int M, int K, int 
     return launch_proj_rm(A, B, C, M, K, nphi, K <= 128 ? proj_rm(K, M) : 0, s);
 }
 
+// Rows per chunk of the instantiated partitioned radial kernel for N_r
+// (capacities whose register arrays stay in VGPRs, no scratch), 0 above
+// N_r = 32 * 20 (then the one-lane kernel k_radial runs).
+int radial_part_capacity(int nr)
+{
+    if (nr > radial::NRMAX) return 0;
+    const int P = nr < radial::PMAX ? nr : radial::PMAX;
+    const int ch = (nr + P - 1) / P;
+    for (int c : {4, 8, 18, 20})
+        if (ch <= c) return c;
+    return 0;
+}
+
 // Partitioned radial solve for N_r <= 32 * 20; returns false above that.
 bool launch_radial_part(double* Y, const double* lam, const double* beta, const double* alpha, const double* V,
                         const double* VR, int nr, int nth, int nphi, hipStream_t s)
 {
-    if (nr > radial::NRMAX) return false;
+    const int cap = radial_part_capacity(nr);
+    if (cap == 0) return false;
     const int P = nr < radial::PMAX ? nr : radial::PMAX;
-    const int ch = (nr + P - 1) / P;
     const radial::Coef cf{alpha, V, VR, nr};
     const int nsys = nphi * nth;
     const dim3 grid((nsys + radial::SYS - 1) / radial::SYS), block(radial::THREADS);
-#define SPP_RADIAL_CASE(C)                                                                             \
-    if (ch <= C) {                                                                                     \
-        hipLaunchKernelGGL(radial::k_radial_part<C>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); \
-        return true;                                                                                   \
+    switch (cap) {
+    case 4: hipLaunchKernelGGL(radial::k_radial_part<4>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
+    case 8: hipLaunchKernelGGL(radial::k_radial_part<8>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
+    case 18: hipLaunchKernelGGL(radial::k_radial_part<18>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
+    default: hipLaunchKernelGGL(radial::k_radial_part<20>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
     }
-    // capacities whose register arrays stay in VGPRs (no scratch) at 1024 threads
-    SPP_RADIAL_CASE(4)
-    SPP_RADIAL_CASE(8)
-    SPP_RADIAL_CASE(18)
-    SPP_RADIAL_CASE(20)
-#undef SPP_RADIAL_CASE
-    return false;
+    return true;
 }
 
 // Fused per-mode kernel (projection, radial solves, inverse projection) on
 // the folded spectrum X, in place; false when the grid is outside its range.
+// Template arguments (column tiles RN, row tiles T) of the fused kernel for
+// this grid; false when it is outside the kernel's range.
+bool modal_variant(int nr, int nth, int* rn, int* T)
+{
+    const int h = nth / 2;
+    *rn = modalimg::rn_for(h);
+    *T = (nr + 16 * modal::NW - 1) / (16 * modal::NW);
+    return !(h % 2 != 0 || h > 64 || *T < 1 || *T > modalimg::TMAX);
+}
+
 bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* Rimg, const double* lam,
                   const double* beta, const radial::Coef& cf, int nr, int nth, int nphi, double* sink,
                   hipStream_t s)
 {
-    const int h = nth / 2;
-    const int rn = modalimg::rn_for(h);
-    const int T = (nr + 16 * modal::NW - 1) / (16 * modal::NW);
-    if (h % 2 != 0 || h > 64 || T < 1 || T > modalimg::TMAX) return false;
+    int rn = 0, T = 0;
+    if (!modal_variant(nr, nth, &rn, &T)) return false;
     const dim3 grid(2 * nphi), block(modal::THREADS);   // one workgroup per (q, parity), see modal::unit_of
 #define SPP_MODAL(RN, TT)                                                                                      \
     case RN * 4 + TT:                                                                                          \
@@ -736,13 +752,13 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
             return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
         mark(1);
         const double* Rimg = reinterpret_cast<const double*>(base + p->lay.Rimg);
-        // the workspace's region after its two fields is the sink of the
+        // the workspace's region after the spectral field is the sink of the
         // per-mode kernel's stores of padding rows and columns
         static_assert(modal::THREADS * sizeof(double) <= spp_modal_sink_bytes, "sink of one workgroup");
         // the kernel reaches the sink by 32-bit byte offsets from each unit's rows
-        if (2 * field + spp_modal_sink_bytes > (size_t(1) << 32))
+        if (field + spp_modal_sink_bytes > (size_t(1) << 32))
             return spp_fail(SPP_ENOTSUP, "spp_solve: field too large for the fused kernel");
-        double* sink = reinterpret_cast<double*>(static_cast<char*>(ws) + 2 * field);
+        double* sink = reinterpret_cast<double*>(static_cast<char*>(ws) + field);
         if (!launch_modal(X, Fimg, Iimg, Rimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, sink, s))
             return spp_fail(SPP_ENOTSUP, "spp_solve: grid outside the fused kernel's range");
         mark(2);
@@ -939,4 +955,28 @@ void spp_prewarm_launch_caches(const spp_plan_s* p)
 #undef SPP_WARM
     default: break;
     }
+}
+
+// Kernels an FP64 solve of this plan launches, in order, named by the same
+// selection rules as spp_launch_solve_f64 (separated by semicolons).
+std::string spp_describe_solve(const spp_plan_s* p)
+{
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    const std::string n = std::to_string(nphi);
+    if (spp_plan_fused(p)) {
+        int rn = 0, T = 0;
+        modal_variant(nr, nth, &rn, &T);
+        return "k_rfft_fwd<" + n + ",fold>;modal::k_modal<" + std::to_string(rn) + "," + std::to_string(T) +
+               ">;k_rfft_inv<" + n + ",fold>";
+    }
+    std::string proj;
+    if (p->par_rn != 0)
+        proj = "proj::k_proj_par<" + std::to_string(p->par_rn) + ">";
+    else if (nth <= 128)
+        proj = "proj::k_proj_f64<" + std::to_string(projimg::rn_for(nth)) + "," + std::to_string(proj_rm(nth, nr)) + ">";
+    else
+        proj = "k_proj_f64";
+    const int cap = radial_part_capacity(nr);
+    const std::string rad = cap ? "radial::k_radial_part<" + std::to_string(cap) + ">" : "k_radial";
+    return "k_rfft_fwd<" + n + ">;" + proj + ";" + rad + ";" + proj + ";k_rfft_inv<" + n + ">";
 }

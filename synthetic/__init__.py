@@ -46,6 +46,34 @@ def theta_interfaces(nth):
     return uniform_interfaces(nth, 0.0, np.pi)
 
 
+def axis_coarsened_theta(nth, ratio=2.0):
+    """Theta interfaces symmetric about the equator whose cells widen towards
+    the poles: the width grows smoothly from the equator to `ratio` times that
+    at the poles (the kind of axis coarsening that relaxes a hydrodynamics
+    code's time step near the axis).  On the northern half, u = j / (nth/2)
+    maps to theta = pi/2 (b u + (1 - b) u^2) with b = 2 ratio / (1 + ratio), whose
+    slope is b at the pole and 2 - b at the equator; the southern half is the
+    mirror image pi - theta (nth even)."""
+    if nth % 2:
+        raise ValueError("nth must be even")
+    h = nth // 2
+    b = 2.0 * ratio / (1.0 + ratio)
+    u = np.arange(h + 1, dtype=np.float64) / h
+    north = 0.5 * np.pi * (b * u + (1.0 - b) * u * u)
+    north[0], north[-1] = 0.0, 0.5 * np.pi
+    return np.concatenate((north, np.pi - north[-2::-1]))
+
+
+def skewed_theta(nth, c=0.3):
+    """Theta interfaces that are smooth but not symmetric about the equator:
+    theta = pi (u + c u (1 - u)) at u = j / nth, so the cells widen from the
+    south pole (width ratio (1 + c)/(1 - c) to the north pole)."""
+    u = np.arange(nth + 1, dtype=np.float64) / nth
+    th = np.pi * (u + c * u * (1.0 - u))
+    th[0], th[-1] = 0.0, np.pi
+    return th
+
+
 def stellar_r_interfaces(nr, n_uniform=20, dr=0.5, r_out=1.0e4):
     """n_uniform zones of width dr from r = 0, then nr - n_uniform zones whose
     widths grow geometrically, dr*q, dr*q^2, ..., with q chosen (by bisection)

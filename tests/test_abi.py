@@ -84,13 +84,23 @@ def test_face_fluxes_argument_checks_on_the_host():
     lib.spp_grid_destroy(g)
 
 
-@pytest.mark.parametrize("nth,nphi,uniform", [(64, 64, True), (128, 256, True), (13, 16, False)])
-def test_host_eigensystems_match_oracle(nth, nphi, uniform):
+@pytest.mark.parametrize("nth,nphi,theta", [(64, 64, "uniform"), (128, 256, "uniform"), (13, 16, "random"),
+                                            (128, 256, "coarsened"), (54, 32, "coarsened")])
+def test_host_eigensystems_match_oracle(nth, nphi, theta):
     """The library's own QL eigensolver against the oracle (LAPACK), compared
-    through what is unique: eigenvalues and the projector sum_l H_l H_l^T D."""
+    through what is unique: eigenvalues and the operator H Lambda H^T D.  On
+    equator-symmetric grids (uniform, or axis-coarsened as in Sec. 6) the
+    library takes the half-size even and odd operators of the parity split
+    (Sec. 4.2): its eigenvectors must be even or odd, and their operator the
+    oracle's full-size one."""
     rng = np.random.default_rng(nth)
-    th_if = synthetic.theta_interfaces(nth) if uniform else np.concatenate(
-        ([0.0], np.sort(rng.uniform(0.1, np.pi - 0.1, nth - 1)), [np.pi]))
+    if theta == "uniform":
+        th_if = synthetic.theta_interfaces(nth)
+    elif theta == "coarsened":
+        th_if = synthetic.axis_coarsened_theta(nth)
+    else:
+        th_if = np.concatenate(([0.0], np.sort(rng.uniform(0.1, np.pi - 0.1, nth - 1)), [np.pi]))
+    symmetric = theta != "random"
     r_if = synthetic.uniform_interfaces(4, 0.0, 1.0)
     st, g = make_grid(r_if, th_if, nphi)
     _check(st, "grid")
@@ -106,7 +116,7 @@ def test_host_eigensystems_match_oracle(nth, nphi, uniform):
         lo, Ho = spectral.theta_eigensystem(geo, m)
         # equator-symmetric grids list the even modes first, then the odd ones
         assert np.max(np.abs(np.sort(lam) - lo)) < 1e-13 * np.max(np.abs(lo))
-        if uniform and nth % 2 == 0:
+        if symmetric:
             h = nth // 2
             assert np.max(np.abs(H[::-1, :h] - H[:, :h])) < 1e-13 * np.max(np.abs(H))
             assert np.max(np.abs(H[::-1, h:] + H[:, h:])) < 1e-13 * np.max(np.abs(H))
@@ -148,9 +158,10 @@ def test_fused_path_range_guard():
 
 
 def test_workspace_holds_the_fused_kernels_store_sink():
-    """A fused plan's FP64 workspace is its two fields plus the per-mode
-    kernel's store sink (one double per thread of its 768-thread workgroup);
-    a staged-only plan needs the two fields."""
+    """A fused plan's FP64 workspace covers both paths: the fused one (one
+    spectral field, then the per-mode kernel's store sink of one double per
+    thread of its 768-thread workgroup) and the staged one (two fields); a
+    staged-only plan needs the two fields."""
     def ws_bytes(r_if, th_if, nphi):
         st, g = make_grid(r_if, th_if, nphi)
         _check(st, "grid")
@@ -165,7 +176,59 @@ def test_workspace_holds_the_fused_kernels_store_sink():
         return wb.value, v.value
     field = 256                                   # 2 x 4 x 4 doubles, 256-byte aligned
     wb, path = ws_bytes(np.array([0.0, 1.0, 2.0]), synthetic.theta_interfaces(4), 4)
-    assert path == 2 and wb == 2 * field + 768 * 8
+    assert path == 2 and wb == max(field + 768 * 8, 2 * field)
     th_ns = np.array([0.0, 0.5, 1.9, np.pi])      # not equator-symmetric: staged only
     wb, path = ws_bytes(np.array([0.0, 1.0, 2.0]), th_ns, 4)
     assert path == 1 and wb == 2 * 256
+
+
+def _host_kernels(r_if, th_if, nphi):
+    st, g = make_grid(r_if, th_if, nphi)
+    _check(st, "grid")
+    p = _vp()
+    _check(lib.spp_plan_create(g, ctypes.byref(p)), "plan")
+    need = ctypes.c_size_t()
+    _check(lib.spp_plan_kernels(p, None, 0, ctypes.byref(need)), "kernels")
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib.spp_plan_kernels(p, buf, need.value, None), "kernels")
+    short = ctypes.create_string_buffer(8)
+    _check(lib.spp_plan_kernels(p, short, 8, None), "kernels")
+    assert short.value == buf.value[:7]
+    lib.spp_plan_destroy(p)
+    lib.spp_grid_destroy(g)
+    return buf.value.decode().split(";")
+
+
+def test_kernel_selection_on_the_host():
+    """The kernels a solve launches follow the documented selection rules
+    (the GPU tests run each of these paths against the oracle)."""
+    rng = np.random.default_rng(0)
+    r = lambda n: np.concatenate(([0.0], np.cumsum(rng.uniform(0.3, 1.7, n))))
+    rand_th = lambda n: np.concatenate(([0.0], np.sort(rng.uniform(0.05, np.pi - 0.05, n - 1)), [np.pi]))
+    assert _host_kernels(r(550), synthetic.theta_interfaces(128), 256) == [
+        "k_rfft_fwd<256,fold>", "modal::k_modal<4,3>", "k_rfft_inv<256,fold>"]
+    assert _host_kernels(r(550), synthetic.axis_coarsened_theta(128), 256)[1] == "modal::k_modal<4,3>"
+    assert _host_kernels(r(12), synthetic.theta_interfaces(144), 16)[1:4] == [
+        "k_proj_f64", "radial::k_radial_part<4>", "k_proj_f64"]
+    assert _host_kernels(r(700), synthetic.theta_interfaces(8), 8)[2] == "k_radial"
+    assert _host_kernels(r(600), synthetic.theta_interfaces(16), 8)[2] == "radial::k_radial_part<20>"
+    assert _host_kernels(r(30), rand_th(100), 16)[1] == "proj::k_proj_f64<8,1>"
+    assert _host_kernels(r(25), rand_th(40), 16)[1] == "proj::k_proj_f64<4,2>"
+    assert _host_kernels(r(20), rand_th(12), 8)[1] == "proj::k_proj_f64<1,4>"
+    assert _host_kernels(r(150), synthetic.axis_coarsened_theta(54), 32)[1:3] == [
+        "proj::k_proj_par<2>", "radial::k_radial_part<8>"]
+
+
+def test_binding_rejects_fields_on_the_wrong_device():
+    """The binding checks every field's dtype, shape, layout and device
+    before anything reaches the C ABI (which sees plain pointers): a CPU
+    tensor passed as rho to a plan on a GPU is refused, also with a valid
+    output.  Checked on a plan object without device buffers."""
+    import torch
+    p = spp.Plan.__new__(spp.Plan)
+    p.nr, p.nth, p.nphi = 3, 4, 8
+    p.device = torch.device("cuda", 0)
+    rho = torch.zeros((3, 4, 8), dtype=torch.float64)
+    for call in (lambda: p.solve(rho), lambda: p.solve_mixed(rho), lambda: p.face_fluxes(rho)):
+        with pytest.raises(ValueError):
+            call()

@@ -122,16 +122,80 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("driver", ["stev", "stemr"])
 @pytest.mark.parametrize("nr,nth,nphi,r0,uni", CASES)
-def test_spectral_matches_dense_brute_force(nr, nth, nphi, r0, uni):
-    """The spectral method reaches the unique solution of the dense system."""
+def test_spectral_matches_dense_brute_force(nr, nth, nphi, r0, uni, driver):
+    """The spectral method reaches the unique solution of the dense system,
+    with either of the oracle's two LAPACK eigensolvers."""
     rng = np.random.default_rng(nr * 100 + nth * 10 + nphi)
     r_if = random_r_if(rng, nr, r0)
     th_if = synthetic.theta_interfaces(nth) if uni else random_th_if(rng, nth)
     rho = rng.standard_normal((nr, nth, nphi))
     ref = dense.solve(r_if, th_if, nphi, rho)
-    got = spectral.solve(r_if, th_if, nphi, rho)
+    got = spectral.solve(r_if, th_if, nphi, rho, driver=driver)
     assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("nr,nth,nphi,r0,uni", [c for c in CASES if c[3] > 0] + [(5, 4, 6, 0.3, False)])
+def test_regular_inner_condition_matches_dense_brute_force(nr, nth, nphi, r0, uni):
+    """With r_{1/2} > 0 and the regular inner condition, the spectral method
+    (gamma(lambda) per eigenmode on the innermost row) reaches the solution of
+    the dense system whose inner face is a matrix function of the directly
+    assembled shell operator; and it differs from the zero-flux solution."""
+    rng = np.random.default_rng(nr * 100 + nth * 10 + nphi + 3)
+    r_if = random_r_if(rng, nr, r0)
+    th_if = synthetic.theta_interfaces(nth) if uni else random_th_if(rng, nth)
+    rho = rng.standard_normal((nr, nth, nphi))
+    ref = dense.solve(r_if, th_if, nphi, rho, inner="regular")
+    assert rel(spectral.solve(r_if, th_if, nphi, rho, inner="regular"), ref) < 1e-13
+    assert rel(spectral.solve(r_if, th_if, nphi, rho), ref) > 1e-3
+
+
+def test_regular_inner_condition_converges_to_free_space_potential():
+    """A Gaussian mass (sigma = 0.18 at r = 0.95) on a grid with a hole
+    r < 0.4: the continuum potential inside the source-free hole is the
+    regular (finite-at-centre) solution, so with the regular inner condition
+    the discrete potential converges at second order to the free-space
+    potential -G M erf(d / (sqrt 2 sigma)) / d; with zero flux through the
+    inner face it does not converge."""
+    from scipy.special import erf
+
+    def err(n, inner):
+        r_if = synthetic.uniform_interfaces(3 * n, 0.4, 2.0)
+        th_if, nphi = synthetic.theta_interfaces(n), 2 * n
+        sig, c = 0.18, (0.95, np.pi / 2, np.pi)
+        rho = synthetic.gaussian_blob(r_if, th_if, nphi, c, sig)
+        phi = spectral.solve(r_if, th_if, nphi, rho, inner=inner)
+        r, th, ph = geometry.cell_centres(r_if, th_if, nphi)
+        R, T, P = np.meshgrid(r, th, ph, indexing="ij")
+        cart = lambda a, b, e: np.array([a * np.sin(b) * np.cos(e), a * np.sin(b) * np.sin(e), a * np.cos(b)])
+        d = np.linalg.norm(cart(R, T, P) - cart(*c)[:, None, None, None], axis=0)
+        exact = -(2 * np.pi * sig ** 2) ** 1.5 * erf(d / (np.sqrt(2) * sig)) / d
+        return float(np.max(np.abs(phi - exact)) / np.max(np.abs(exact)))
+
+    reg = [err(n, "regular") for n in (16, 32, 64)]
+    assert reg[2] < 3e-3
+    assert 3.0 < reg[0] / reg[1] < 4.5 and 3.5 < reg[1] / reg[2] < 4.5
+    zf = [err(n, "zero_flux") for n in (16, 64)]
+    assert zf[1] > 0.05 and zf[1] > 0.5 * zf[0]
+
+
+def test_regular_inner_pin_catches_planted_mistakes(monkeypatch):
+    """Slips in the inner-face coefficient fail the dense pin."""
+    rng = np.random.default_rng(99)
+    r_if, th_if, nphi = random_r_if(rng, 4, 0.6), random_th_if(rng, 4), 5
+    rho = rng.standard_normal((4, 4, nphi))
+    ref = dense.solve(r_if, th_if, nphi, rho, inner="regular")
+    ok = lambda: rel(spectral.solve(r_if, th_if, nphi, rho, inner="regular"), ref) < 1e-13
+    assert ok()
+    orig = spectral.inner_gamma
+    for slip in (lambda g, lam, inner="zero_flux": -orig(g, lam, inner),
+                 lambda g, lam, inner="zero_flux": orig(g, lam, inner) * g["r"][0] / g["r_if"][0],
+                 lambda g, lam, inner="zero_flux": orig(g, 2.0 * np.asarray(lam), inner)):
+        monkeypatch.setattr(spectral, "inner_gamma", slip)
+        assert not ok()
+        monkeypatch.undo()
+    assert ok()
 
 
 def test_dense_operator_is_volume_symmetric():
@@ -188,6 +252,55 @@ def test_uniform_sphere_second_order():
         errs.append(np.max(np.abs(phi[:, 0, 0] - ex)) / np.max(np.abs(ex)))
     assert errs[0] < 1e-3
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+@pytest.mark.parametrize("inner", ["zero_flux", "regular"])
+@pytest.mark.parametrize("nr,nth,nphi,r0,uni", CASES)
+def test_stencil_and_backward_error_denominator_match_dense_operator(nr, nth, nphi, r0, uni, inner):
+    """laplacian.apply against the operator assembled cell by cell (dense):
+    L Phi = (L_local + L_outer) Phi, and the denominator of the componentwise
+    backward error is |L_local| |Phi| + |L_outer Phi| (the nonlocal outer-face
+    term enters as one term, its value's magnitude) -- on random fields,
+    including the outer shell, offset inner radii and non-uniform theta."""
+    rng = np.random.default_rng(nr * 100 + nth * 10 + nphi + 7)
+    r_if = random_r_if(rng, nr, r0)
+    th_if = synthetic.theta_interfaces(nth) if uni else random_th_if(rng, nth)
+    P = rng.standard_normal((nr, nth, nphi))
+    Lloc, Lout = dense.assemble_parts(r_if, th_if, nphi, inner)
+    x = P.reshape(-1)
+    LP, mag = laplacian.apply(r_if, th_if, nphi, P, with_terms=True, inner=inner)
+    want_mag = np.abs(Lloc) @ np.abs(x) + np.abs(Lout @ x)
+    assert np.max(np.abs(LP.reshape(-1) - (Lloc + Lout) @ x)) < 1e-13 * np.max(want_mag)
+    assert np.max(np.abs(mag.reshape(-1) - want_mag) / want_mag) < 1e-13
+    # the outer shell's denominator carries the boundary term: it differs
+    # from the local part alone
+    outer = slice((nr - 1) * nth * nphi, None)
+    assert np.max(np.abs(Lout @ x)[outer]) > 1e-3 * np.max(want_mag[outer])
+
+
+def test_backward_error_denominator_pin_catches_slips(monkeypatch):
+    """A slip in the outer-face term of laplacian (mirrored shell, or the
+    term dropped from the denominator) fails the dense pin above."""
+    rng = np.random.default_rng(17)
+    nr, nth, nphi = 4, 5, 6
+    r_if, th_if = random_r_if(rng, nr), random_th_if(rng, nth)
+    P = rng.standard_normal((nr, nth, nphi))
+    Lloc, Lout = dense.assemble_parts(r_if, th_if, nphi)
+    x = P.reshape(-1)
+    want_mag = np.abs(Lloc) @ np.abs(x) + np.abs(Lout @ x)
+
+    def ok():
+        LP, mag = laplacian.apply(r_if, th_if, nphi, P, with_terms=True)
+        return (np.max(np.abs(LP.reshape(-1) - (Lloc + Lout) @ x)) < 1e-13 * np.max(want_mag)
+                and np.max(np.abs(mag.reshape(-1) - want_mag) / want_mag) < 1e-13)
+
+    assert ok()
+    orig = laplacian.outer_flux
+    for slip in (lambda g, s: orig(g, s[:, ::-1]), lambda g, s: 2.0 * orig(g, s)):
+        monkeypatch.setattr(laplacian, "outer_flux", slip)
+        assert not ok()
+        monkeypatch.undo()
+    assert ok()
 
 
 def test_componentwise_backward_error_at_roundoff():
@@ -426,8 +539,6 @@ def test_ellipsoid_accuracy_matches_paper():
     assert abs(e3 / g["max_rel_err"] - 1.0) <= g["tolerance_fraction"], e3
 
 
-@pytest.mark.slow
-@pytest.mark.skipif(not os.environ.get("SPP_SLOW_TESTS"), reason="about 90 s; set SPP_SLOW_TESTS=1 to run")
 def test_ellipsoid_radial_jump_matches_paper():
     """Sec. 5.2: 50% larger radial spacing outside r = 1.5 -> 3.6e-5 (within 30%)."""
     with open(os.path.join(GOLDEN, "ellipsoid_convergence.json")) as fh:
