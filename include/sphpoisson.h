@@ -155,6 +155,26 @@ spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double 
                      void* workspace_dev, void* stream);
 
 /*
+ * spp_solve without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  The same kernels and result as spp_solve; the
+ * workspace is the library's own device scratch of SPP_NOALLOC_SCRATCH_BYTES
+ * (160 MiB), one copy per device, held by every device the library runs on
+ * until the process ends.  The call allocates nothing (no hipMalloc, no
+ * allocating library routine) and clears nothing: a solve writes its whole
+ * workspace before reading it.  Every call on one device uses that device's
+ * one scratch: calls that overlap on a device (several streams or threads)
+ * race and must be serialised by the caller (one stream, or events).
+ * Limit: the plan's current path must need at most SPP_NOALLOC_SCRATCH_BYTES
+ * of workspace -- the fused path one field of N_r N_theta N_phi doubles plus
+ * 6 KB (the 550 x 128 x 256 grid: 137.5 MiB), the staged path two fields.
+ * Arguments as spp_solve.  Errors: as spp_solve; SPP_ENOTSUP when the plan
+ * needs more scratch; SPP_EDEVICE when the scratch address cannot be found.
+ */
+#define SPP_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+spp_status spp_solve_noalloc(spp_plan p, const double* rho_dev, double* phi_dev, double G, void* stream);
+
+/*
  * Face fluxes of grad Phi through every cell face, enqueued on `stream`
  * (Sec. 3.1: the operator is a finite-volume divergence, (Delta Phi) delta V =
  * the sum over a cell's six faces of area x difference quotient; Sec. 3.2 for

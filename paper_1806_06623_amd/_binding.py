@@ -35,6 +35,8 @@ lib.spp_plan_upload.argtypes = [_vp, _vp, _vp]
 lib.spp_plan_upload.restype = _c_int
 lib.spp_solve.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp]
 lib.spp_solve.restype = _c_int
+lib.spp_solve_noalloc.argtypes = [_vp, _vp, _vp, _c_double, _vp]
+lib.spp_solve_noalloc.restype = _c_int
 lib.spp_solve_profiled.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp, _dp]
 lib.spp_solve_profiled.restype = _c_int
 lib.spp_face_fluxes.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -219,6 +221,19 @@ class Plan:
         self._check_workspace(ws, self.workspace_bytes)
         _check(lib.spp_solve(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
                              _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_solve")
+        return out
+
+    def solve_noalloc(self, rho, G=1.0, out=None, stream=None):
+        """spp_solve_noalloc: the solve with the library's own device scratch
+        as workspace (no allocation by the library; `out` is allocated here
+        when not given).  Calls overlapping on one device race."""
+        import torch
+        self._check_field(rho, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        self._check_field(out, "out")
+        _check(lib.spp_solve_noalloc(self._plan, _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G),
+                                     _stream_ptr(stream)), "spp_solve_noalloc")
         return out
 
     def face_fluxes(self, phi, out=None, workspace=None, stream=None):

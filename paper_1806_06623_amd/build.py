@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsphpoisson.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "eigen_ql.cpp", "solve.hip", "batch.cpp", "server.cpp"]
+SOURCES = ["plan.cpp", "eigen_ql.cpp", "solve.hip", "batch.cpp", "server.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-result"]

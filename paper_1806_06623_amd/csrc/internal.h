@@ -87,6 +87,10 @@ spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double
 spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* stream, int* chosen_rm);
 void spp_prewarm_launch_caches(const spp_plan_s* p);
 
+// Resolve the no-allocation solve's scratch address on the current device
+// (noalloc.hip; called by spp_plan_upload).
+void spp_noalloc_prepare_current_device();
+
 // Kernels of an FP64 solve of this plan, separated by semicolons (solve.hip).
 std::string spp_describe_solve(const spp_plan_s* p);
 

@@ -594,6 +594,7 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     if (e != hipSuccess)
         return spp_fail(SPP_EDEVICE, std::string("spp_plan_upload: ") + hipGetErrorString(e));
     p->dev = plan_dev;
+    spp_noalloc_prepare_current_device();
     return SPP_OK;
 }
 
