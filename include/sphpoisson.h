@@ -12,8 +12,8 @@
  *     = s^ with the asymptotic outer boundary condition     (Sec. 3.2)
  *   inverse projection and inverse FFT                      (Sec. 3.2)
  * The discrete operator is the finite-volume Laplacian of Sec. 3.1 with
- * zero-area pole faces, periodic phi, zero flux through the inner radial
- * face (zero area when r_{1/2} = 0) and the outer condition above; the solver
+ * zero-area pole faces, periodic phi, the inner radial face of spp_inner_bc
+ * (zero area when r_{1/2} = 0) and the outer condition above; the solver
  * returns its unique solution.
  *
  * Conventions shared by every call:
@@ -45,8 +45,22 @@ typedef enum {
     SPP_EDEVICE = -3,    /* a HIP call failed                                   */
     SPP_ENOMEM = -4,     /* host allocation failed                              */
     SPP_ESTATE = -5,     /* object used out of order (e.g. solve before upload) */
-    SPP_ENONFINITE = -6  /* non-finite value detected                           */
+    SPP_ENONFINITE = -6, /* non-finite value detected                           */
+    SPP_ENOCONV = -7     /* refinement did not contract (FP64 fallback disabled) */
 } spp_status;
+
+/* Inner radial face r_{1/2} (the paper does not fix it; it matters only when
+ * r_{1/2} > 0, since a face at r = 0 has no area). */
+typedef enum {
+    SPP_INNER_AUTO = 0,      /* zero area when r_{1/2} = 0, else zero flux             */
+    SPP_INNER_ZERO_FLUX = 1, /* no flux through the inner face (exact for l = 0 when
+                                no mass lies inside r_{1/2})                         */
+    SPP_INNER_REGULAR = 2    /* the source-free interior's regular solution: each
+                                angular eigenmode decays inwards as r^p',
+                                p' = (-1 + sqrt(1 - 4 lambda_Omega))/2, extrapolated
+                                from the innermost zone to the face (the counterpart of
+                                the outer condition of Sec. 3.2)                     */
+} spp_inner_bc;
 
 typedef enum {
     SPP_FP64 = 0,          /* all stages in float64                                */
@@ -61,6 +75,18 @@ typedef enum {
     SPP_PATH_STAGED = 1,   /* five kernels: FFT, projection, radial, projection, FFT */
     SPP_PATH_FUSED = 2     /* folded FFT, one per-mode kernel, folded inverse FFT  */
 } spp_path;
+
+/* What a solve found, read back by spp_solve_status after the stream ran. */
+typedef struct {
+    int refine_iters;              /* refinement steps taken (mixed form; 0 for FP64)   */
+    double first_residual_rel;     /* max|s - L g_0| / max|s| after the first low-
+                                      precision pass (mixed form; 0 for FP64)           */
+    double last_residual_rel;      /* max|s - L g_n-1| / max|s|, the residual the last
+                                      correction was computed from (mixed form)         */
+    int not_contracted;            /* some refinement step had max|r_k| > max|r_k-1| / 2 */
+    int fell_back_fp64;            /* the FP64 solve replaced the mixed result           */
+    int nonfinite;                 /* Phi holds a NaN or an infinity                     */
+} spp_solve_info;
 
 typedef struct spp_grid_s* spp_grid;   /* host geometry, immutable        */
 typedef struct spp_plan_s* spp_plan;   /* eigensystems + device layout    */
@@ -101,12 +127,14 @@ typedef struct {
  *          the cells need not be uniform (the separation of variables does not
  *          require it, Sec. 3.1);
  *   nphi   uniform phi cells; the GPU path needs a power of two in [4, 2048]
- *          (SPP_ENOTSUP otherwise).
+ *          (SPP_ENOTSUP otherwise);
+ *   inner  the inner radial face condition (spp_inner_bc).
  * The interface arrays are copied. *out receives the new grid.
- * Errors: SPP_EINVAL for the conditions above or NULL pointers.
+ * Errors: SPP_EINVAL for the conditions above, an unknown `inner` or NULL
+ * pointers.
  */
 spp_status spp_grid_create(int nr, const double* r_if, int nth, const double* th_if,
-                           int nphi, spp_grid* out);
+                           int nphi, spp_inner_bc inner, spp_grid* out);
 void spp_grid_destroy(spp_grid g);
 
 /*
@@ -128,7 +156,9 @@ void spp_plan_destroy(spp_plan p);
  *   *plan_bytes       one buffer per plan, written by spp_plan_upload and
  *                     read-only afterwards (eigenvector matrices, tables);
  *   *workspace_bytes  scratch for one solve in flight; concurrent solves on
- *                     different streams need separate workspaces.
+ *                     different streams need separate workspaces.  Its first
+ *                     256 bytes hold the status record of the last solve
+ *                     enqueued on it (spp_solve_status).
  * Both are multiples of 256 bytes; buffers must be 256-byte aligned.
  */
 spp_status spp_plan_device_bytes(spp_plan p, size_t* plan_bytes, size_t* workspace_bytes);
@@ -149,10 +179,47 @@ spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream);
  *   G        the gravitational constant in the caller's units;
  *   workspace_dev  device scratch of workspace_bytes (256-byte aligned).
  * Errors (synchronous, nothing enqueued): SPP_EINVAL (NULL/misaligned/alias),
- * SPP_ESTATE (plan not uploaded), SPP_EDEVICE (launch failure).
+ * SPP_ESTATE (plan not uploaded), SPP_EDEVICE (launch failure).  A non-finite
+ * value of Phi (from a NaN or infinity in rho, or an overflow) is recorded on
+ * the device and reported by spp_solve_status.
  */
 spp_status spp_solve(spp_plan p, const double* rho_dev, double* phi_dev, double G,
                      void* workspace_dev, void* stream);
+
+/*
+ * Outcome of the last solve enqueued on `workspace_dev` (spp_solve,
+ * spp_solve_mixed; spp_solve_noalloc with workspace_dev NULL): synchronises
+ * `stream`, then reads the status record the solve's kernels wrote into the
+ * workspace's first 256 bytes (the scratch of spp_solve_noalloc when
+ * workspace_dev is NULL).
+ *   info  host, may be NULL; receives the record (spp_solve_info).
+ * Returns SPP_ENONFINITE if Phi holds a NaN or an infinity, SPP_ENOCONV if a
+ * refinement step of the mixed form did not contract and its FP64 fallback
+ * was disabled (Phi is then the unconverged mixed result), otherwise SPP_OK
+ * (also when the fallback replaced the result: info->fell_back_fp64 = 1).
+ * Errors: SPP_EINVAL (NULL plan), SPP_EDEVICE (synchronisation or copy).
+ */
+spp_status spp_solve_status(spp_plan p, const void* workspace_dev, void* stream, spp_solve_info* info);
+
+/*
+ * The FP64 residual of Phi, enqueued on `stream`:
+ *   r = 4 pi G rho - L Phi,
+ * L the discrete operator of Sec. 3.1 (the local flux stencil, divided by the
+ * cell volume) with the outer boundary face of Sec. 3.2 (and the inner face of
+ * the grid's inner condition) applied per angular eigenmode of the outermost
+ * (innermost) shell.  For Phi from spp_solve, |r| is at rounding level of
+ * |L||Phi| + |4 pi G rho| componentwise.
+ *   rho_dev, phi_dev  device, [N_r][N_theta][N_phi] float64, read-only;
+ *   r_dev             device, same shape, written (disjoint from both);
+ *   workspace_dev     any FP64 workspace of the plan (256-byte aligned); the
+ *                     call uses four shells of N_theta N_phi doubles after its
+ *                     status record, which it leaves alone.
+ * Errors (synchronous, nothing enqueued): SPP_EINVAL (NULL, misaligned,
+ * overlap), SPP_ESTATE (plan not uploaded), SPP_ENOTSUP (N_theta > 3840),
+ * SPP_EDEVICE (launch failure).
+ */
+spp_status spp_residual(spp_plan p, const double* rho_dev, const double* phi_dev, double G, double* r_dev,
+                        void* workspace_dev, void* stream);
 
 /*
  * spp_solve without a workspace argument, for callers that cannot allocate
@@ -208,7 +275,8 @@ spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double* fr_dev, do
 
 /*
  * Workspace bytes of one solve in flight for a given precision (SPP_FP64: as
- * spp_plan_device_bytes; SPP_MIXED_FP32: four fields plus one shell).
+ * spp_plan_device_bytes; SPP_MIXED_FP32: the status record, four fields, two
+ * shells and the residual maxima, at least the FP64 fallback's workspace).
  * Errors: SPP_EINVAL (NULL), SPP_ENOTSUP (precision not built).
  */
 spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, size_t* bytes);
@@ -223,18 +291,34 @@ spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, size_t* byte
  *   n_refine times: r = s~ - L g with L the FP64 discrete Laplacian of each
  *        Fourier component (local flux stencil of Sec. 3.1 plus the outer
  *        boundary term of Sec. 3.2), then g += H F^-1 H^-1 r as above;
- *   Phi = inverse FFT of g in FP64.
+ *   Phi = inverse FFT of g in FP64;
+ * then a contraction check on the device: every refinement step must have
+ * max|r_k| <= max|r_k-1| / 2 (r_0 = s~).  If one does not and fallback_fp64 is
+ * non-zero, the FP64 solve (spp_solve's kernels, enqueued behind and gated on
+ * the device) replaces Phi; spp_solve_status reports which happened.
  * Each FP32 pass has a relative error near 1e-7; one refinement brings the
  * result to the FP64 solution within ~1e-12 on the workloads tested.
  *   prec           SPP_MIXED_FP32 (SPP_FP64 runs spp_solve);
  *   n_refine       0..16 refinement steps;
+ *   fallback_fp64  non-zero: the FP64 solve replaces a result whose
+ *                  refinement did not contract;
  *   workspace_dev  spp_plan_workspace_bytes(p, prec) bytes, 256-byte aligned;
  * other arguments as spp_solve.  Needs N_theta <= 128 (SPP_ENOTSUP otherwise).
  * Errors: as spp_solve, plus SPP_EINVAL for n_refine out of range and
  * SPP_ENOTSUP for an unsupported precision.
  */
-spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const double* rho_dev,
+spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, int fallback_fp64, const double* rho_dev,
                            double* phi_dev, double G, void* workspace_dev, void* stream);
+
+/*
+ * For tests of the refinement's failure handling: multiply the host copies of
+ * the low-precision eigenvector images the mixed form uses by `factor` (the
+ * FP64 tables are untouched); takes effect at the next spp_plan_upload.  A
+ * factor c makes each low-precision pass return about c^2 times its
+ * correction, so that the refinement diverges for c^2 > 2.
+ * Errors: SPP_EINVAL (NULL plan, non-finite factor).
+ */
+spp_status spp_plan_scale_lowprec_basis(spp_plan p, double factor);
 
 /*
  * spp_solve with per-stage timing, for benchmarks and profiling.  Records

@@ -21,7 +21,7 @@ lib = ctypes.CDLL(LIB_PATH)
 _c_int, _c_double, _c_size_t, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 
-lib.spp_grid_create.argtypes = [_c_int, _dp, _c_int, _dp, _c_int, ctypes.POINTER(_vp)]
+lib.spp_grid_create.argtypes = [_c_int, _dp, _c_int, _dp, _c_int, _c_int, ctypes.POINTER(_vp)]
 lib.spp_grid_create.restype = _c_int
 lib.spp_grid_destroy.argtypes = [_vp]
 lib.spp_grid_destroy.restype = None
@@ -43,8 +43,21 @@ lib.spp_face_fluxes.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 lib.spp_face_fluxes.restype = _c_int
 lib.spp_plan_workspace_bytes.argtypes = [_vp, _c_int, ctypes.POINTER(_c_size_t)]
 lib.spp_plan_workspace_bytes.restype = _c_int
-lib.spp_solve_mixed.argtypes = [_vp, _c_int, _c_int, _vp, _vp, _c_double, _vp, _vp]
+lib.spp_solve_mixed.argtypes = [_vp, _c_int, _c_int, _c_int, _vp, _vp, _c_double, _vp, _vp]
 lib.spp_solve_mixed.restype = _c_int
+lib.spp_residual.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp, _vp]
+lib.spp_residual.restype = _c_int
+lib.spp_plan_scale_lowprec_basis.argtypes = [_vp, _c_double]
+lib.spp_plan_scale_lowprec_basis.restype = _c_int
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("refine_iters", _c_int), ("first_residual_rel", _c_double), ("last_residual_rel", _c_double),
+                ("not_contracted", _c_int), ("fell_back_fp64", _c_int), ("nonfinite", _c_int)]
+
+
+lib.spp_solve_status.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_SolveInfo)]
+lib.spp_solve_status.restype = _c_int
 lib.spp_autotune_projection.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_c_int)]
 lib.spp_autotune_projection.restype = _c_int
 _vpp = ctypes.POINTER(_vp)
@@ -98,6 +111,9 @@ lib.spp_last_error.argtypes = []
 lib.spp_last_error.restype = ctypes.c_char_p
 
 precision_codes = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16x3": 2}
+inner_codes = {"auto": 0, "zero_flux": 1, "regular": 2}
+STATUS_NAMES = {0: "ok", -1: "einval", -2: "enotsup", -3: "edevice", -4: "enomem", -5: "estate",
+                -6: "enonfinite", -7: "enoconv"}
 
 
 class SphPoissonError(RuntimeError):
@@ -132,13 +148,13 @@ class Plan:
     torch stream and returns Phi (float64, same shape as rho).
     """
 
-    def __init__(self, r_if, th_if, nphi, device="cuda"):
+    def __init__(self, r_if, th_if, nphi, device="cuda", inner="auto"):
         import torch
         r_if, rp = _f64(r_if)
         th_if, tp = _f64(th_if)
         self.nr, self.nth, self.nphi = r_if.size - 1, th_if.size - 1, int(nphi)
         grid = _vp()
-        _check(lib.spp_grid_create(self.nr, rp, self.nth, tp, self.nphi, ctypes.byref(grid)),
+        _check(lib.spp_grid_create(self.nr, rp, self.nth, tp, self.nphi, inner_codes[inner], ctypes.byref(grid)),
                "spp_grid_create")
         plan = _vp()
         try:
@@ -263,7 +279,7 @@ class Plan:
         return b.value
 
     def solve_mixed(self, rho, G=1.0, precision="mixed_fp32", n_refine=1, out=None, workspace=None,
-                    stream=None):
+                    stream=None, fallback_fp64=True):
         """Mixed-precision solve with FP64 refinement (see spp_solve_mixed)."""
         import torch
         self._check_field(rho, "rho")
@@ -276,10 +292,55 @@ class Plan:
                 self._mixed_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
             workspace = self._mixed_ws
         self._check_workspace(workspace, need)
-        _check(lib.spp_solve_mixed(self._plan, precision_codes[precision], int(n_refine), _vp(rho.data_ptr()),
-                                   _vp(out.data_ptr()), float(G), _vp(workspace.data_ptr()),
+        _check(lib.spp_solve_mixed(self._plan, precision_codes[precision], int(n_refine), int(bool(fallback_fp64)),
+                                   _vp(rho.data_ptr()), _vp(out.data_ptr()), float(G), _vp(workspace.data_ptr()),
                                    _stream_ptr(stream)), "spp_solve_mixed")
         return out
+
+    @property
+    def mixed_workspace(self):
+        """The workspace solve_mixed allocated for itself (None before its first call)."""
+        return getattr(self, "_mixed_ws", None)
+
+    def status(self, workspace=None, noalloc=False, stream=None):
+        """spp_solve_status of the last solve on `workspace` (default: the
+        plan's own workspace; noalloc=True: the no-allocation scratch).
+        Synchronises the stream; returns a dict with the status name and the
+        spp_solve_info fields."""
+        if noalloc:
+            ptr = None
+        else:
+            ws = self.workspace if workspace is None else workspace
+            ptr = _vp(ws.data_ptr())
+        info = _SolveInfo()
+        st = lib.spp_solve_status(self._plan, ptr, _stream_ptr(stream), ctypes.byref(info))
+        if st not in (0, -6, -7):
+            _check(st, "spp_solve_status")
+        d = {f: getattr(info, f) for f, _ in _SolveInfo._fields_}
+        d["status"] = STATUS_NAMES.get(st, st)
+        return d
+
+    def residual(self, rho, phi, G=1.0, out=None, workspace=None, stream=None):
+        """r = 4 pi G rho - L Phi in FP64 (spp_residual)."""
+        import torch
+        self._check_field(rho, "rho")
+        self._check_field(phi, "phi")
+        if out is None:
+            out = torch.empty_like(phi)
+        self._check_field(out, "out")
+        ws = self.workspace if workspace is None else workspace
+        self._check_workspace(ws, self.workspace_bytes)
+        _check(lib.spp_residual(self._plan, _vp(rho.data_ptr()), _vp(phi.data_ptr()), float(G), _vp(out.data_ptr()),
+                                _vp(ws.data_ptr()), _stream_ptr(stream)), "spp_residual")
+        return out
+
+    def scale_lowprec_basis(self, factor):
+        """Test hook: scale the low-precision eigenvector images and upload the
+        plan again (spp_plan_scale_lowprec_basis)."""
+        _check(lib.spp_plan_scale_lowprec_basis(self._plan, float(factor)), "spp_plan_scale_lowprec_basis")
+        with torch.cuda.device(self.device):
+            _check(lib.spp_plan_upload(self._plan, _vp(self._plan_dev.data_ptr()), _stream_ptr(None)),
+                   "spp_plan_upload")
 
     def solve_profiled(self, rho, out, G=1.0, stream=None):
         """One solve with per-stage HIP-event timing; blocks until done.

@@ -10,9 +10,11 @@
 
 #include "modal_layout.h"
 #include "sphpoisson.h"
+#include "status.h"
 
 struct spp_grid_s {
     int nr = 0, nth = 0, nphi = 0;
+    spp_inner_bc inner = SPP_INNER_AUTO;
     std::vector<double> r_if, th_if;
 };
 
@@ -23,6 +25,7 @@ struct spp_plan_layout {
     size_t H = 0;       // inverse projection, [M][N_theta(j)][N_theta(l)]
     size_t lam = 0;     // lambda_Omega, [M][N_theta]
     size_t beta = 0;    // outer-boundary coefficient, [M][N_theta]
+    size_t gamma = 0;   // inner-boundary coefficient (regular inner condition), [M][N_theta]
     size_t alpha = 0;   // radial face coefficients, [N_r] (last entry 0)
     size_t V = 0;       // radial volume factors, [N_r]
     size_t VR = 0;      // V_i R_i, [N_r]
@@ -46,7 +49,8 @@ struct spp_plan_s {
     int nr = 0, nth = 0, nphi = 0, nm = 0;   // nm = N_phi/2 + 1 azimuthal modes
     std::vector<double> r_if, th_if;
     // host tables (float64), layouts as in spp_plan_layout
-    std::vector<double> tw, W, H, lam, beta, alpha, V, VR, Wimg, Himg, sig, dmu, Sj, lamphi;
+    std::vector<double> tw, W, H, lam, beta, gamma, alpha, V, VR, Wimg, Himg, sig, dmu, Sj, lamphi;
+    bool inner_regular = false;                // regular inner condition with r_{1/2} > 0
     std::vector<float> Wimg32, Himg32;
     std::vector<double> Ue, Uo, Wpar, Hpar;   // half-size even/odd eigenvectors and their images
     int proj_rn = 0;                           // tile width of the projection kernel (0: fallback)
@@ -65,18 +69,26 @@ spp_status spp_fail(spp_status st, const std::string& msg);
 
 // Device entry of the FP64 solve (solve.hip).  With ev != NULL, ev[0..5]
 // are recorded on the stream before the first and after every stage.
+// With gate != NULL every kernel runs only if *gate != 0 (status.h); such a
+// solve does not clear the workspace's status record.
 spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* phi, double G,
-                                void* ws, void* stream, hipEvent_t* ev = nullptr);
+                                void* ws, void* stream, hipEvent_t* ev = nullptr, const unsigned* gate = nullptr);
 
 // Number of timed stages of one solve and their names.
 constexpr int SPP_NUM_STAGES = 5;
 
 // Device entry of the mixed-precision solve (solve.hip).
-spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision prec, int n_refine, const double* rho,
-                                  double* phi, double G, void* ws, void* stream);
+spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision prec, int n_refine, int fallback_fp64,
+                                  const double* rho, double* phi, double G, void* ws, void* stream);
 
-// Workspace of the mixed-precision solve: four fields and one outer shell.
+// Workspace of the mixed-precision solve: the status record, four fields, two
+// shells and the residual maxima (and at least the FP64 fallback's workspace).
 size_t spp_mixed_workspace_bytes(const spp_plan_s* p);
+
+// Device entry of the FP64 residual r = 4 pi G rho - L Phi (solve.hip); the
+// workspace needs four shells after its status record.
+spp_status spp_launch_residual(const spp_plan_s* p, const double* rho, const double* phi, double G, double* r,
+                               void* ws, void* stream);
 
 // Device entry of the face fluxes of grad Phi (solve.hip); the workspace needs
 // two shells of N_theta N_phi doubles (any FP64 solve workspace holds them).
@@ -88,8 +100,9 @@ spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* str
 void spp_prewarm_launch_caches(const spp_plan_s* p);
 
 // Resolve the no-allocation solve's scratch address on the current device
-// (noalloc.hip; called by spp_plan_upload).
+// (noalloc.hip; called by spp_plan_upload), and look it up.
 void spp_noalloc_prepare_current_device();
+spp_status spp_noalloc_scratch_current(void** ptr);
 
 // Kernels of an FP64 solve of this plan, separated by semicolons (solve.hip).
 std::string spp_describe_solve(const spp_plan_s* p);
@@ -115,13 +128,14 @@ constexpr size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }
 // (nothing reads them).
 constexpr size_t spp_modal_sink_bytes = spp_align256(size_t(modalimg::NW) * 64 * sizeof(double));
 
-// Workspace bytes of one FP64 solve on the fused path (one spectral field,
-// transformed in place, then the store sink) or on the staged path (two
-// fields); either also holds the two shells of spp_face_fluxes.
+// Workspace bytes of one FP64 solve: the status record (status.h), then on
+// the fused path one spectral field, transformed in place, and the store
+// sink, on the staged path two fields; either also holds the four shells of
+// spp_residual (two of which spp_face_fluxes uses).
 inline size_t spp_path_workspace_bytes(const spp_plan_s* p, bool fused)
 {
     const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
-    const size_t shells = 2 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
+    const size_t shells = 4 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
     const size_t need = (fused && p->fused_ok) ? field + spp_modal_sink_bytes : 2 * field;
-    return need > shells ? need : shells;
+    return SPP_STATUS_BYTES + (need > shells ? need : shells);
 }

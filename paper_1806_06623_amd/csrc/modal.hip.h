@@ -47,6 +47,7 @@
 
 #include "modal_layout.h"
 #include "radial.hip.h"
+#include "status.h"
 
 namespace modal {
 
@@ -266,8 +267,10 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
                                                    const double* __restrict__ Iimg, const double* __restrict__ Rimg,
                                                    const double* __restrict__ lam,
                                                    const double* __restrict__ beta, radial::Coef tab, int nth,
-                                                   int nphi, double* __restrict__ sink)
+                                                   int nphi, double* __restrict__ sink,
+                                                   const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
     using Gm = Geo<RN>;
     constexpr int NC = Gm::NC, ELEMS = Gm::ELEMS;
     constexpr int CH = 4 * T;               // rows per lane chunk

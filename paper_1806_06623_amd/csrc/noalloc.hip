@@ -45,6 +45,8 @@ spp_status scratch_on_current_device(void** out)
 
 }  // namespace
 
+spp_status spp_noalloc_scratch_current(void** ptr) { return scratch_on_current_device(ptr); }
+
 // Set-up hook (spp_plan_upload, with the plan's device current): resolve the
 // scratch address of this device before the first no-allocation solve.  A
 // failure here is not an error of the upload; the entry point reports it.

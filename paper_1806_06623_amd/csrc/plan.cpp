@@ -27,10 +27,12 @@ static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 // ---------------------------------------------------------------- grid
 extern "C" spp_status spp_grid_create(int nr, const double* r_if, int nth, const double* th_if,
-                                      int nphi, spp_grid* out)
+                                      int nphi, spp_inner_bc inner, spp_grid* out)
 {
     if (!out || !r_if || !th_if) return spp_fail(SPP_EINVAL, "spp_grid_create: NULL pointer");
     *out = nullptr;
+    if (inner != SPP_INNER_AUTO && inner != SPP_INNER_ZERO_FLUX && inner != SPP_INNER_REGULAR)
+        return spp_fail(SPP_EINVAL, "spp_grid_create: unknown inner boundary condition");
     if (nr < 2 || nth < 2 || nphi < 2)
         return spp_fail(SPP_EINVAL, "spp_grid_create: need nr >= 2, nth >= 2, nphi >= 2");
     if (!(r_if[0] >= 0.0)) return spp_fail(SPP_EINVAL, "spp_grid_create: r_if[0] must be >= 0");
@@ -47,6 +49,7 @@ extern "C" spp_status spp_grid_create(int nr, const double* r_if, int nth, const
     g->nr = nr;
     g->nth = nth;
     g->nphi = nphi;
+    g->inner = inner;
     g->r_if.assign(r_if, r_if + nr + 1);
     g->th_if.assign(th_if, th_if + nth + 1);
     g->th_if.front() = 0.0;
@@ -248,6 +251,12 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         p->H.assign(size_t(nm) * nth * nth, 0.0);
         p->lam.assign(size_t(nm) * nth, 0.0);
         p->beta.assign(size_t(nm) * nth, 0.0);
+        p->gamma.assign(size_t(nm) * nth, 0.0);
+        // regular inner condition (the paper leaves the inner face open; with
+        // r_{1/2} = 0 the face has no area and needs no condition)
+        const double ri = g->r_if[0], r1 = G.r[0];
+        p->inner_regular = g->inner == SPP_INNER_REGULAR && ri > 0.0;
+        const double log_in = p->inner_regular ? std::log(ri / r1) : 0.0;
         const double dphi = 2.0 * M_PI / nphi;
         const double ro = g->r_if[nr], rn = G.r[nr - 1];
         const double log_ratio = std::log(ro / rn);
@@ -309,6 +318,12 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             // beta = p r_o (r_o / r_N)^-p, p = (1 + sqrt(1 - 4 lambda))/2
             const double pp = 0.5 * (1.0 + std::sqrt(std::max(0.0, 1.0 - 4.0 * lam)));
             p->beta[size_t(m) * nth + l] = pp * ro * std::exp(-pp * log_ratio);
+            // inner face: flux / (dmu dphi) = gamma f_1 with gamma = p' r_i (r_i/r_1)^p',
+            // p' = (-1 + sqrt(1 - 4 lambda))/2, the regular interior solution r^p'
+            if (p->inner_regular) {
+                const double pi = pp - 1.0;
+                p->gamma[size_t(m) * nth + l] = pi * ri * std::exp(pi * log_in);
+            }
         };
         auto work = [&](int m0, int stride) {
             std::vector<double> d(nth), e(nth > 1 ? nth - 1 : 0), Z;
@@ -429,7 +444,9 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         // the interleaved k order of modal_layout.h):
         //   forward  B_p[k = j][n = l] = U_p[j][l] dmu_j / sqrt 2
         //   inverse  B_p[k = l][n = j] = U_p[j][l] / sqrt 2
-        p->fused_ok = symmetric && hh % 2 == 0 && hh <= 64 && nr <= modalimg::NRMAX &&
+        // the fused kernel's row records have no inner-face term: grids with the
+        // regular inner condition take the staged kernels
+        p->fused_ok = symmetric && hh % 2 == 0 && hh <= 64 && nr <= modalimg::NRMAX && !p->inner_regular &&
                       modal_continuants_in_range(p->alpha, p->VR, p->lam, p->beta, nr);
         if (p->fused_ok) {
             const int rn = modalimg::rn_for(hh);
@@ -470,6 +487,7 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.H = take(p->H.size());
         L.lam = take(p->lam.size());
         L.beta = take(p->beta.size());
+        L.gamma = take(p->gamma.size());
         L.alpha = take(p->alpha.size());
         L.V = take(p->V.size());
         L.VR = take(p->VR.size());
@@ -572,6 +590,7 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.H, p->H);
     put(p->lay.lam, p->lam);
     put(p->lay.beta, p->beta);
+    put(p->lay.gamma, p->gamma);
     put(p->lay.alpha, p->alpha);
     put(p->lay.V, p->V);
     put(p->lay.VR, p->VR);
@@ -640,16 +659,83 @@ extern "C" spp_status spp_plan_workspace_bytes(spp_plan p, spp_precision prec, s
     return SPP_OK;
 }
 
-extern "C" spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, const double* rho_dev,
-                                      double* phi_dev, double G, void* workspace_dev, void* stream)
+extern "C" spp_status spp_solve_mixed(spp_plan p, spp_precision prec, int n_refine, int fallback_fp64,
+                                      const double* rho_dev, double* phi_dev, double G, void* workspace_dev,
+                                      void* stream)
 {
     const spp_status st = spp_validate_solve("spp_solve_mixed", p, rho_dev, phi_dev, G, workspace_dev);
     if (st != SPP_OK) return st;
     if (prec == SPP_FP64) return spp_launch_solve_f64(p, rho_dev, phi_dev, G, workspace_dev, stream);
     if (prec != SPP_MIXED_FP32) return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: precision not supported");
-    if (n_refine < 0 || n_refine > 16) return spp_fail(SPP_EINVAL, "spp_solve_mixed: n_refine must be in [0, 16]");
+    if (n_refine < 0 || n_refine > SPP_MAX_REFINE)
+        return spp_fail(SPP_EINVAL, "spp_solve_mixed: n_refine must be in [0, 16]");
     if (p->proj_rn == 0) return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: needs N_theta <= 128");
-    return spp_launch_solve_mixed(p, prec, n_refine, rho_dev, phi_dev, G, workspace_dev, stream);
+    return spp_launch_solve_mixed(p, prec, n_refine, fallback_fp64, rho_dev, phi_dev, G, workspace_dev, stream);
+}
+
+extern "C" spp_status spp_plan_scale_lowprec_basis(spp_plan p, double factor)
+{
+    if (!p || !std::isfinite(factor)) return spp_fail(SPP_EINVAL, "spp_plan_scale_lowprec_basis: bad arguments");
+    for (auto& v : p->Wimg32) v = float(v * factor);
+    for (auto& v : p->Himg32) v = float(v * factor);
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_solve_status(spp_plan p, const void* workspace_dev, void* stream, spp_solve_info* info)
+{
+    if (!p) return spp_fail(SPP_EINVAL, "spp_solve_status: NULL plan");
+    const void* rec_dev = workspace_dev;
+    if (!rec_dev) {
+        void* scratch = nullptr;
+        const spp_status st = spp_noalloc_scratch_current(&scratch);
+        if (st != SPP_OK) return st;
+        rec_dev = scratch;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    spp_status_record rec{};
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(&rec, rec_dev, sizeof(rec), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve_status: ") + hipGetErrorString(e));
+    auto dbl = [](unsigned long long b) {
+        double d;
+        std::memcpy(&d, &b, sizeof(d));
+        return d;
+    };
+    const int n = int(std::min<unsigned>(rec.refine_iters, SPP_MAX_REFINE));
+    const double s0 = dbl(rec.rmax[0]);
+    if (info) {
+        info->refine_iters = n;
+        info->first_residual_rel = n > 0 && s0 > 0.0 ? dbl(rec.rmax[1]) / s0 : 0.0;
+        info->last_residual_rel = n > 0 && s0 > 0.0 ? dbl(rec.rmax[n]) / s0 : 0.0;
+        info->not_contracted = rec.not_contracted ? 1 : 0;
+        info->fell_back_fp64 = rec.fallback ? 1 : 0;
+        info->nonfinite = rec.nonfinite ? 1 : 0;
+    }
+    if (rec.nonfinite) return spp_fail(SPP_ENONFINITE, "spp_solve_status: Phi holds a non-finite value");
+    if (rec.not_contracted && !rec.fallback)
+        return spp_fail(SPP_ENOCONV, "spp_solve_status: the refinement did not contract (FP64 fallback disabled)");
+    return SPP_OK;
+}
+
+extern "C" spp_status spp_residual(spp_plan p, const double* rho_dev, const double* phi_dev, double G,
+                                   double* r_dev, void* workspace_dev, void* stream)
+{
+    if (!p || !rho_dev || !phi_dev || !r_dev || !workspace_dev)
+        return spp_fail(SPP_EINVAL, "spp_residual: NULL pointer");
+    if (!p->dev) return spp_fail(SPP_ESTATE, "spp_residual: plan not uploaded");
+    if (reinterpret_cast<uintptr_t>(workspace_dev) & 255)
+        return spp_fail(SPP_EINVAL, "spp_residual: workspace must be 256-byte aligned");
+    if (!std::isfinite(G)) return spp_fail(SPP_EINVAL, "spp_residual: G must be finite");
+    const size_t n = size_t(p->nr) * p->nth * p->nphi * sizeof(double);
+    const size_t wsn = SPP_STATUS_BYTES + 4 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
+    const char* r = reinterpret_cast<const char*>(r_dev);
+    const char* in[2] = {reinterpret_cast<const char*>(rho_dev), reinterpret_cast<const char*>(phi_dev)};
+    const char* w = static_cast<const char*>(workspace_dev);
+    for (const char* x : in)
+        if (r < x + n && x < r + n) return spp_fail(SPP_EINVAL, "spp_residual: r must not overlap rho or phi");
+    for (const char* x : {in[0], in[1], r})
+        if (x < w + wsn && w < x + n) return spp_fail(SPP_EINVAL, "spp_residual: the workspace overlaps a field");
+    return spp_launch_residual(p, rho_dev, phi_dev, G, r_dev, workspace_dev, stream);
 }
 
 extern "C" spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double* fr_dev, double* ft_dev,
@@ -663,8 +749,9 @@ extern "C" spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double*
     const size_t n = size_t(p->nr) * p->nth * p->nphi * sizeof(double);
     const char* b[4] = {reinterpret_cast<const char*>(phi_dev), reinterpret_cast<const char*>(fr_dev),
                         reinterpret_cast<const char*>(ft_dev), reinterpret_cast<const char*>(fp_dev)};
-    // the part of the workspace the call uses: two shells of N_theta N_phi doubles
-    const size_t wsn = 2 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
+    // the part of the workspace the call uses: the status record, then two
+    // shells of N_theta N_phi doubles
+    const size_t wsn = SPP_STATUS_BYTES + 2 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
     const char* wsb = static_cast<const char*>(workspace_dev);
     for (int x = 0; x < 4; ++x) {
         if (reinterpret_cast<uintptr_t>(b[x]) & 15)

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "proj_layout.h"
+#include "status.h"
 
 namespace proj {
 
@@ -91,8 +92,10 @@ constexpr int NWAVES = 8;                 // two waves per SIMD share one LDS co
 
 template <int RN, int RM, bool KVEC, int NW = NWAVES>
 __global__ __launch_bounds__(64 * NW) void k_proj_f64(const double* __restrict__ A, const double* __restrict__ Bimg,
-                                                  double* __restrict__ C, int M, int K, int nphi, int splits)
+                                                  double* __restrict__ C, int M, int K, int nphi, int splits,
+                                                  const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
     using S = Shape<RN>;
     __shared__ double Bs[S::KMAX * S::NP];
 
@@ -239,8 +242,10 @@ __device__ __forceinline__ void mfma_chunk_par(d4 (&ae)[RM][RN], d4 (&ao)[RM][RN
 
 template <int RN, int RM, bool KVEC, bool FWD, int NW = NWAVES>
 __global__ __launch_bounds__(64 * NW) void k_proj_par(const double* __restrict__ A, const double* __restrict__ Bpar,
-                                                      double* __restrict__ C, int M, int N, int nphi, int splits)
+                                                      double* __restrict__ C, int M, int N, int nphi, int splits,
+                                                      const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
     using S = Shape<RN>;
     __shared__ double Bs[2 * S::ELEMS];
 

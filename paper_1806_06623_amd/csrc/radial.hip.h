@@ -18,6 +18,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "status.h"
+
 namespace radial {
 
 constexpr int SYS = 16;     // systems per workgroup (consecutive (q, l) pairs)
@@ -31,6 +33,8 @@ struct Coef {
     const double* V;
     const double* VR;
     int nr;
+    const double* gamma;    // inner-face coefficient gamma(lambda), [M][N_theta] (zero
+                            // unless the regular inner condition with r_{1/2} > 0)
 };
 
 // Per-row coefficients staged in LDS once per workgroup.
@@ -39,10 +43,11 @@ struct RowCoef {
     const double* VR;       // LDS
     int nr;
     __device__ __forceinline__ double off(int i) const { return alpha[i]; }
-    // diagonal of row i for eigenvalue lm and outer coefficient bo
-    __device__ __forceinline__ double diag(int i, double lm, double bo) const
+    // diagonal of row i for eigenvalue lm, outer coefficient bo and inner
+    // coefficient gi (the innermost row's missing coupling is gi)
+    __device__ __forceinline__ double diag(int i, double lm, double bo, double gi) const
     {
-        const double am = i > 0 ? alpha[i - 1] : 0.0;
+        const double am = i > 0 ? alpha[i - 1] : gi;
         double b = -(am + alpha[i]) + VR[i] * lm;
         if (i == nr - 1) b -= bo;
         return b;
@@ -66,8 +71,9 @@ __device__ __forceinline__ double recip(double w)
 template <int CH>
 __global__ __launch_bounds__(THREADS, 4) void k_radial_part(double* __restrict__ Y, const double* __restrict__ lam,
                                                       const double* __restrict__ beta, Coef tab, int nth,
-                                                      int nphi, int P)
+                                                      int nphi, int P, const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
     __shared__ double own[3][PMAX][SYS];   // separator row p: B (diag part), C, D
     __shared__ double nxt[3][PMAX][SYS];   // contribution of chunk p to row p+1: A, B add, D sub
     __shared__ double red[4][PMAX][SYS];   // reduced rows (A, B, C, D) during cyclic reduction
@@ -90,6 +96,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_radial_part(double* __restrict__
     const int m = q <= nphi / 2 ? q : nphi - q;
     const double lm = lam[m * nth + l];
     const double bo = beta[m * nth + l];
+    const double gi = tab.gamma[m * nth + l];
     const bool active = p < P;
 
     const int s0 = active ? (p * nr) / P : 0;
@@ -126,13 +133,13 @@ __global__ __launch_bounds__(THREADS, 4) void k_radial_part(double* __restrict__
             if (k <= n) {
                 const int i = s0 + k;
                 if (k == 1) {
-                    w = cf.diag(i, lm, bo);
+                    w = cf.diag(i, lm, bo, gi);
                     zf = d[1];
                     uf = -oL;
                 } else {
                     const double o = cf.off(i - 1);
                     const double mult = o * invw[k - 1];
-                    w = cf.diag(i, lm, bo) - mult * o;
+                    w = cf.diag(i, lm, bo, gi) - mult * o;
                     zf = d[k] - mult * zf;
                     uf = -mult * uf;
                 }
@@ -150,13 +157,13 @@ __global__ __launch_bounds__(THREADS, 4) void k_radial_part(double* __restrict__
             if (k <= n) {
                 const int i = s0 + k;
                 if (k == n) {
-                    wh = cf.diag(i, lm, bo);
+                    wh = cf.diag(i, lm, bo, gi);
                     zh = d[k];
                     vh = -oR;
                 } else {
                     const double o = cf.off(i);
                     const double mult = o * iwh;
-                    wh = cf.diag(i, lm, bo) - mult * o;
+                    wh = cf.diag(i, lm, bo, gi) - mult * o;
                     zh = d[k] - mult * zh;
                     vh = -mult * vh;
                 }
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_radial_part(double* __restrict__
 
     // ---- reduced system over the separators s_0..s_{P-1}
     if (active) {
-        const double bs = cf.diag(s0, lm, bo);
+        const double bs = cf.diag(s0, lm, bo, gi);
         own[0][p][sl] = bs + oL * Uf;
         own[1][p][sl] = oL * Vf;
         own[2][p][sl] = d[0] - oL * Yf;

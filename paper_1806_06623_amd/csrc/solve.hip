@@ -23,8 +23,15 @@
 #include "modal.hip.h"
 #include "proj.hip.h"
 #include "radial.hip.h"
+#include "status.h"
 
 namespace {
+
+// True unless both values are finite (a NaN fails every comparison).
+__device__ __forceinline__ bool nonfinite2(double a, double b)
+{
+    return !(__builtin_fabs(a) <= 1.7976931348623157e308 && __builtin_fabs(b) <= 1.7976931348623157e308);
+}
 
 // ------------------------------------------------------------------ FFT
 // Persistent workgroups: each one loops over blocks of JB lines and keeps the
@@ -41,8 +48,11 @@ namespace {
 template <int N, bool FOLD = false, bool PERSIST = true>
 __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
                                                   const c64* __restrict__ tw_g, double scale, int nlines,
-                                                  int nblocks, int nth)
+                                                  int nblocks, int nth, spp_status_record* __restrict__ reset,
+                                                  const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
+    spp_status_clear(reset);
     constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
     using S = FftShape<N, TH>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
@@ -157,10 +167,16 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(
 // With FOLD the block's lines are the even and odd folds (i, k), (i, h+k)
 // of JB/2 pairs; it stores their sum as line (i, k) and their difference as
 // line (i, N_theta-1-k).
+// A workgroup that stores a non-finite value sets flag->nonfinite (when
+// flag is not NULL).
 template <int N, bool FOLD = false, bool PERSIST = true>
 __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
-                                                  const c64* __restrict__ tw_g, int nlines, int nblocks, int nth)
+                                                  const c64* __restrict__ tw_g, int nlines, int nblocks, int nth,
+                                                  spp_status_record* __restrict__ flag,
+                                                  const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
+    bool bad = false;
     constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
     using S = FftShape<N, TH>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
@@ -243,6 +259,7 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
                     const unsigned i = P / unsigned(h), k = P - i * unsigned(h);
                     const c64 ve = lds[(e / N2) * LS + pidx(e % N2)];
                     const c64 vo = lds[(PB + e / N2) * LS + pidx(e % N2)];
+                    bad = bad || nonfinite2(ve.x + vo.x, ve.y + vo.y) || nonfinite2(ve.x - vo.x, ve.y - vo.y);
                     dst[(size_t(i) * nth + k) * N2 + e % N2] = double2{ve.x + vo.x, -(ve.y + vo.y)};
                     dst[(size_t(i) * nth + nth - 1 - k) * N2 + e % N2] = double2{ve.x - vo.x, -(ve.y - vo.y)};
                 }
@@ -256,6 +273,7 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
                 const int e = threadIdx.x + TH * u;
                 if (e < nl * N2) {
                     const c64 v = lds[(e / N2) * LS + pidx(e % N2)];
+                    bad = bad || nonfinite2(v.x, v.y);
                     dst[e] = double2{v.x, -v.y};
                 }
             }
@@ -263,6 +281,7 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
         __syncthreads();
         if constexpr (!PERSIST) break;
     }
+    if (bad && flag) atomicOr(&flag->nonfinite, 1u);
 }
 
 // ------------------------------------------------------------------ projection GEMM (MFMA f64)
@@ -275,8 +294,10 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
 constexpr int PBM = 64, PBN = 64, PBK = 16, PPAD = 16;
 
 __global__ __launch_bounds__(256) void k_proj_f64(const double* __restrict__ A, const double* __restrict__ B,
-                                                  double* __restrict__ C, int M, int K, int nphi)
+                                                  double* __restrict__ C, int M, int K, int nphi,
+                                                  const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
     const int q = blockIdx.z;
     const int m = q <= nphi / 2 ? q : nphi - q;
     const double* Aq = A + size_t(q) * M * K;
@@ -344,20 +365,25 @@ __global__ __launch_bounds__(256) void k_proj_f64(const double* __restrict__ A, 
 // One lane per (q, l) system; rows scaled by V_i so the matrix is symmetric:
 //   alpha_{i-1} f_{i-1} + (-(alpha_{i-1} + alpha_i) + V_i R_i lambda) f_i
 //     + alpha_i f_{i+1} = V_i s^_i,
-// with alpha_{-1} = 0 and the outermost alpha replaced by beta(lambda).
+// with alpha_{-1} replaced by gamma(lambda) (0 unless the regular inner
+// condition) and the outermost alpha by beta(lambda).
 // Forward elimination stores y_i in place and 1/w_i in `piv`; the back
 // substitution then runs from the outer shell inwards.
 __global__ __launch_bounds__(256) void k_radial(double* __restrict__ Y, double* __restrict__ piv,
                                                 const double* __restrict__ lam, const double* __restrict__ beta,
+                                                const double* __restrict__ gamma,
                                                 const double* __restrict__ alpha, const double* __restrict__ V,
-                                                const double* __restrict__ VR, int nr, int nth, int nphi)
+                                                const double* __restrict__ VR, int nr, int nth, int nphi,
+                                                const unsigned* __restrict__ gate)
 {
+    if (spp_gate_closed(gate)) return;
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nphi * nth) return;
     const int q = gid / nth, l = gid - q * nth;
     const int m = q <= nphi / 2 ? q : nphi - q;
     const double lm = lam[m * nth + l];
     const double bo = beta[m * nth + l];
+    const double gi = gamma[m * nth + l];
     const size_t stride = size_t(nth);
     double* y = Y + size_t(q) * nr * nth + l;
     double* pv = piv + size_t(q) * nr * nth + l;
@@ -365,7 +391,7 @@ __global__ __launch_bounds__(256) void k_radial(double* __restrict__ Y, double* 
     double a_prev = 0.0, w_prev = 1.0, y_prev = 0.0, inv_prev = 0.0;
     for (int i = 0; i < nr; ++i) {
         const double ai = (i + 1 < nr) ? alpha[i] : bo;
-        const double diag = -(a_prev + ai) + VR[i] * lm;
+        const double diag = -((i == 0 ? gi : a_prev) + ai) + VR[i] * lm;
         const double rhs = V[i] * y[i * stride];
         const double lf = a_prev * inv_prev;          // a_prev / w_prev
         const double w = diag - lf * a_prev;
@@ -426,7 +452,8 @@ std::vector<int> proj_rm_candidates(int rn)
     }
 }
 
-bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, int nphi, int rm, hipStream_t s)
+bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, int nphi, int rm, hipStream_t s,
+                    const unsigned* gate = nullptr)
 {
     if (K > 128) return false;
     const int rn = projimg::rn_for(K);
@@ -443,9 +470,11 @@ bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, i
 #define SPP_PROJ(RN, RM)                                                                                       \
     do {                                                                                                       \
         if (kvec)                                                                                              \
-            hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, true>), grid, block, 0, s, A, B, C, M, K, nphi, splits);  \
+            hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, true>), grid, block, 0, s, A, B, C, M, K, nphi, splits,   \
+                               gate);                                                                          \
         else                                                                                                   \
-            hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, false>), grid, block, 0, s, A, B, C, M, K, nphi, splits); \
+            hipLaunchKernelGGL((proj::k_proj_f64<RN, RM, false>), grid, block, 0, s, A, B, C, M, K, nphi, splits,  \
+                               gate);                                                                          \
     } while (0)
     if (rn == 8) {
         if (rm == 2) SPP_PROJ(8, 2); else SPP_PROJ(8, 1);
@@ -462,7 +491,7 @@ bool launch_proj_rm(const double* A, const double* B, double* C, int M, int K, i
 
 // Parity-split projection for equator-symmetric theta grids (h = N_theta/2 <= 64).
 bool launch_proj_par(const double* A, const double* Bpar, double* C, int M, int N, int nphi, bool fwd, int rn,
-                     hipStream_t s)
+                     hipStream_t s, const unsigned* gate = nullptr)
 {
     if (rn == 0) return false;
     const int h = N / 2;
@@ -477,9 +506,11 @@ bool launch_proj_par(const double* A, const double* Bpar, double* C, int M, int 
 #define SPP_PAR(RN, KV)                                                                                        \
     do {                                                                                                       \
         if (fwd)                                                                                               \
-            hipLaunchKernelGGL((proj::k_proj_par<RN, 1, KV, true>), grid, block, 0, s, A, Bpar, C, M, N, nphi, splits);  \
+            hipLaunchKernelGGL((proj::k_proj_par<RN, 1, KV, true>), grid, block, 0, s, A, Bpar, C, M, N, nphi, splits,   \
+                               gate);                                                                          \
         else                                                                                                   \
-            hipLaunchKernelGGL((proj::k_proj_par<RN, 1, KV, false>), grid, block, 0, s, A, Bpar, C, M, N, nphi, splits); \
+            hipLaunchKernelGGL((proj::k_proj_par<RN, 1, KV, false>), grid, block, 0, s, A, Bpar, C, M, N, nphi, splits,  \
+                               gate);                                                                          \
     } while (0)
     switch (rn) {
     case 1: if (kvec) SPP_PAR(1, true); else SPP_PAR(1, false); break;
@@ -491,9 +522,10 @@ bool launch_proj_par(const double* A, const double* Bpar, double* C, int M, int 
 }
 
 // Projection GEMM with B_m staged in LDS for N_theta <= 128; false above.
-bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s)
+bool launch_proj(const double* A, const double* B, double* C, int M, int K, int nphi, hipStream_t s,
+                 const unsigned* gate = nullptr)
 {
-    return launch_proj_rm(A, B, C, M, K, nphi, K <= 128 ? proj_rm(K, M) : 0, s);
+    return launch_proj_rm(A, B, C, M, K, nphi, K <= 128 ? proj_rm(K, M) : 0, s, gate);
 }
 
 // Rows per chunk of the instantiated partitioned radial kernel for N_r
@@ -510,20 +542,20 @@ int radial_part_capacity(int nr)
 }
 
 // Partitioned radial solve for N_r <= 32 * 20; returns false above that.
-bool launch_radial_part(double* Y, const double* lam, const double* beta, const double* alpha, const double* V,
-                        const double* VR, int nr, int nth, int nphi, hipStream_t s)
+bool launch_radial_part(double* Y, const double* lam, const double* beta, const radial::Coef& cf, int nth,
+                        int nphi, hipStream_t s, const unsigned* gate = nullptr)
 {
+    const int nr = cf.nr;
     const int cap = radial_part_capacity(nr);
     if (cap == 0) return false;
     const int P = nr < radial::PMAX ? nr : radial::PMAX;
-    const radial::Coef cf{alpha, V, VR, nr};
     const int nsys = nphi * nth;
     const dim3 grid((nsys + radial::SYS - 1) / radial::SYS), block(radial::THREADS);
     switch (cap) {
-    case 4: hipLaunchKernelGGL(radial::k_radial_part<4>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
-    case 8: hipLaunchKernelGGL(radial::k_radial_part<8>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
-    case 18: hipLaunchKernelGGL(radial::k_radial_part<18>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
-    default: hipLaunchKernelGGL(radial::k_radial_part<20>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P); break;
+    case 4: hipLaunchKernelGGL(radial::k_radial_part<4>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P, gate); break;
+    case 8: hipLaunchKernelGGL(radial::k_radial_part<8>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P, gate); break;
+    case 18: hipLaunchKernelGGL(radial::k_radial_part<18>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P, gate); break;
+    default: hipLaunchKernelGGL(radial::k_radial_part<20>, grid, block, 0, s, Y, lam, beta, cf, nth, nphi, P, gate); break;
     }
     return true;
 }
@@ -542,7 +574,7 @@ bool modal_variant(int nr, int nth, int* rn, int* T)
 
 bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* Rimg, const double* lam,
                   const double* beta, const radial::Coef& cf, int nr, int nth, int nphi, double* sink,
-                  hipStream_t s)
+                  hipStream_t s, const unsigned* gate = nullptr)
 {
     int rn = 0, T = 0;
     if (!modal_variant(nr, nth, &rn, &T)) return false;
@@ -550,7 +582,7 @@ bool launch_modal(double* X, const double* Fimg, const double* Iimg, const doubl
 #define SPP_MODAL(RN, TT)                                                                                      \
     case RN * 4 + TT:                                                                                          \
         hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, Rimg, lam, beta, cf, nth, nphi, \
-                           sink);                                                                              \
+                           sink, gate);                                                                        \
         return true;
     switch (rn * 4 + T) {
         SPP_MODAL(1, 1)
@@ -588,9 +620,16 @@ int fft_resident(bool forward, bool fold)
     return res;
 }
 
+// rec: the forward FFT clears this status record first, the inverse FFT sets
+// its non-finite flag (either may be NULL); gate: see status.h.
+struct FftExtra {
+    spp_status_record* rec = nullptr;
+    const unsigned* gate = nullptr;
+};
+
 template <int N>
 void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
-                     bool fold, int nth, hipStream_t s)
+                     bool fold, int nth, hipStream_t s, FftExtra x)
 {
     const int per_block = fold ? FftShape<N, 512>::JB / 2 : FftShape<N, 256>::JB;
     const int units = fold ? nlines / 2 : nlines;
@@ -602,27 +641,27 @@ void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw,
     if (forward) {
         if (fold)   // one block per workgroup (see k_rfft_fwd)
             hipLaunchKernelGGL((k_rfft_fwd<N, true, false>), dim3(nblocks), dim3(512), 0, s, in, out, tw, scale,
-                               nlines, nblocks, nth);
+                               nlines, nblocks, nth, x.rec, x.gate);
         else
             hipLaunchKernelGGL((k_rfft_fwd<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
-                               nblocks, nth);
+                               nblocks, nth, x.rec, x.gate);
     } else {
         if (fold)
             hipLaunchKernelGGL((k_rfft_inv<N, true, false>), dim3(nblocks), dim3(512), 0, s, in, out, tw, nlines,
-                               nblocks, nth);
+                               nblocks, nth, x.rec, x.gate);
         else
             hipLaunchKernelGGL((k_rfft_inv<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
-                               nth);
+                               nth, x.rec, x.gate);
     }
 }
 
 // fold: the line-pair layout of the fused per-mode path (equator-symmetric grids)
 bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64* tw, double scale, int nlines,
-                hipStream_t s, bool fold = false, int nth = 0)
+                hipStream_t s, bool fold = false, int nth = 0, FftExtra x = {})
 {
     switch (nphi) {
 #define SPP_FFT_CASE(n) \
-    case n: launch_fft_pair<n>(forward, in, out, tw, scale, nlines, fold, nth, s); return true;
+    case n: launch_fft_pair<n>(forward, in, out, tw, scale, nlines, fold, nth, s, x); return true;
         SPP_FFT_CASE(4)
         SPP_FFT_CASE(8)
         SPP_FFT_CASE(16)
@@ -638,13 +677,21 @@ bool launch_fft(int nphi, bool forward, const double* in, double* out, const c64
     }
 }
 
-// ------------------------------------------------------------------ mixed precision: FP64 residual
-// The refinement works on the Fourier components: the phi operator is
-// diagonal there (eigenvalue lambda_{phi,m}), so the discrete Laplacian of
-// component q is a local operator in (i, j) plus, on the outermost shell, the
-// boundary term of Sec. 3.2, which acts per theta eigenmode.
+// Fill n 64-bit words with zero (a kernel, so that the fill can be captured
+// into a graph).
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict__ x, size_t n)
+{
+    const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) x[i] = 0ull;
+}
 
-// r = s~ - L_q g for every element (q, i, j), FP64.
+// ------------------------------------------------------------------ residuals
+// The refinement of the mixed form works on the Fourier components: the phi
+// operator is diagonal there (eigenvalue lambda_{phi,m}), so the discrete
+// Laplacian of component q is a local operator in (i, j) plus, on the
+// outermost shell, the boundary term of Sec. 3.2 (and on the innermost shell
+// the regular inner condition's term), which act per theta eigenmode.
+
 struct ResidualTables {
     const double* alpha;   // [nr], alpha[nr-1] = 0
     const double* V;       // [nr]
@@ -655,32 +702,177 @@ struct ResidualTables {
     const double* lamphi;  // [nphi/2 + 1]
 };
 
-// 256 consecutive elements of one component plane per workgroup (32-bit index
-// arithmetic only).
-__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ St, const double* __restrict__ Gf,
-                                                  const double* __restrict__ ob, double* __restrict__ R,
-                                                  ResidualTables t, int nr, int nth, int nphi)
+// Largest |x| over a workgroup of 256 threads, NaN winning (a NaN compares
+// false, so it is tracked apart); the result as IEEE-754 bits, which order
+// non-negative doubles and put NaN above infinity.
+__device__ __forceinline__ unsigned long long block_absmax_bits(double v, bool nan, double* red)
 {
-    const int el = blockIdx.x * 256 + threadIdx.x;
-    if (el >= nr * nth) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double m = nan ? __builtin_nan("") : v;
+    unsigned long long bits = __double_as_longlong(m);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(bits, o, 64);
+        bits = other > bits ? other : bits;
+    }
+    if (lane == 0) red[w] = __longlong_as_double(bits);
+    __syncthreads();
+    unsigned long long out = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) {
+            const unsigned long long b = __double_as_longlong(red[k]);
+            out = b > out ? b : out;
+        }
+    return out;
+}
+
+// r = s~ - L_q g for every element (q, i, j), FP64.  Workgroups (x, q) stride
+// over the plane of component q; each adds max |r| of its elements into
+// rmax_q[q] (and max |s~| into smax_q[q] when not NULL) with one atomic.
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ St, const double* __restrict__ Gf,
+                                                  const double* __restrict__ ob, const double* __restrict__ ib,
+                                                  double* __restrict__ R, ResidualTables t, int nr, int nth,
+                                                  int nphi, unsigned long long* __restrict__ rmax_q,
+                                                  unsigned long long* __restrict__ smax_q)
+{
+    __shared__ double red[4];
     const int q = blockIdx.y;
-    const int i = el / nth, j = el - i * nth;
     const int m = q <= nphi / 2 ? q : nphi - q;
-    const size_t e = size_t(q) * nr * nth + el;
-    const double g0 = Gf[e];
-    // radial fluxes through the faces i+1/2 and i-1/2 (outer face: boundary term)
-    double flux = 0.0;
-    if (i + 1 < nr) flux += t.alpha[i] * (Gf[e + nth] - g0);
-    else flux -= ob[size_t(q) * nth + j];
-    if (i > 0) flux -= t.alpha[i - 1] * (g0 - Gf[e - nth]);
-    const double Vi = t.V[i];
-    // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
-    double th = 0.0;
-    if (j + 1 < nth) th += t.sig[j + 1] * (Gf[e + 1] - g0);
-    if (j > 0) th -= t.sig[j] * (g0 - Gf[e - 1]);
-    const double Ri = t.VR[i] / Vi;
-    const double Lg = flux / Vi + Ri * (th / t.dmu[j] + t.Sj[j] * t.lamphi[m] * g0);
-    R[e] = St[e] - Lg;
+    const int plane = nr * nth;
+    double mr = 0.0, ms = 0.0;
+    bool nr_nan = false, ns_nan = false;
+    for (int el = blockIdx.x * 256 + threadIdx.x; el < plane; el += gridDim.x * 256) {
+        const int i = el / nth, j = el - i * nth;
+        const size_t e = size_t(q) * plane + el;
+        const double g0 = Gf[e];
+        // radial fluxes through the faces i+1/2 and i-1/2 (outer face: boundary
+        // term; inner face: the regular condition's term, 0 for zero flux)
+        double flux = 0.0;
+        if (i + 1 < nr) flux += t.alpha[i] * (Gf[e + nth] - g0);
+        else flux -= ob[size_t(q) * nth + j];
+        if (i > 0) flux -= t.alpha[i - 1] * (g0 - Gf[e - nth]);
+        else if (ib) flux -= ib[size_t(q) * nth + j];
+        const double Vi = t.V[i];
+        // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
+        double th = 0.0;
+        if (j + 1 < nth) th += t.sig[j + 1] * (Gf[e + 1] - g0);
+        if (j > 0) th -= t.sig[j] * (g0 - Gf[e - 1]);
+        const double Ri = t.VR[i] / Vi;
+        const double Lg = flux / Vi + Ri * (th / t.dmu[j] + t.Sj[j] * t.lamphi[m] * g0);
+        const double s = St[e];
+        const double r = s - Lg;
+        R[e] = r;
+        const double ar = __builtin_fabs(r), as = __builtin_fabs(s);
+        nr_nan |= ar != ar;
+        mr = ar > mr ? ar : mr;
+        ns_nan |= as != as;
+        ms = as > ms ? as : ms;
+    }
+    const unsigned long long br = block_absmax_bits(mr, nr_nan, red);
+    if (threadIdx.x == 0) atomicMax(rmax_q + q, br);
+    if (smax_q) {
+        __syncthreads();
+        const unsigned long long bs = block_absmax_bits(ms, ns_nan, red);
+        if (threadIdx.x == 0) atomicMax(smax_q + q, bs);
+    }
+}
+
+// After the refinement of the mixed form: reduce the per-component maxima
+// of each residual (part[k][q], k = 0: the source, k = 1..n: the residuals
+// the corrections were computed from) into the status record and decide.
+// Refinement step k contracted if max |r_k| <= max |r_{k-1}| / 2 (finite);
+// if any step did not, the record says so and, with allow_fallback, opens
+// the gate of the FP64 solve enqueued behind (whose inverse FFT then sets the
+// non-finite flag afresh).  One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_refine_gate(spp_status_record* __restrict__ rec,
+                                                     const unsigned long long* __restrict__ part, int nphi,
+                                                     int n_refine, int allow_fallback)
+{
+    __shared__ double red[4];
+    __shared__ unsigned long long kmax[SPP_MAX_REFINE + 1];
+    for (int k = 0; k <= n_refine; ++k) {
+        unsigned long long mb = 0;
+        for (int q = threadIdx.x; q < nphi; q += 256) {
+            const unsigned long long b = part[size_t(k) * nphi + q];
+            mb = b > mb ? b : mb;
+        }
+        const double v = __longlong_as_double(mb);
+        const unsigned long long r = block_absmax_bits(v, v != v, red);
+        if (threadIdx.x == 0) kmax[k] = r;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        unsigned bad = 0;
+        for (int k = 1; k <= n_refine; ++k) {
+            const double rk = __longlong_as_double(kmax[k]), rp = __longlong_as_double(kmax[k - 1]);
+            if (!(rk <= 0.5 * rp)) bad = 1;      // NaN or infinity fail too
+        }
+        for (int k = 0; k <= n_refine; ++k) rec->rmax[k] = kmax[k];
+        rec->refine_iters = unsigned(n_refine);
+        rec->not_contracted = bad;
+        const unsigned fb = bad && allow_fallback ? 1u : 0u;
+        rec->fallback = fb;
+        if (fb) rec->nonfinite = 0u;
+    }
+}
+
+// r = 4 pi G rho - L Phi in physical space (spp_residual), FP64: the flux
+// stencil of Sec. 3.1 divided by the cell volume,
+//   L Phi = [F_{i+1/2} - F_{i-1/2}] / V_i
+//         + R_i [sigma_{j+1/2} (Phi_{j+1} - Phi_j) - sigma_{j-1/2} (Phi_j - Phi_{j-1})] / dmu_j
+//         + R_i S_j (Phi_{k+1} - 2 Phi_k + Phi_{k-1}) / dphi^2,
+// F_{i+1/2} = alpha_i (Phi_{i+1} - Phi_i) inside, -T_out on the outer face and
+// T_in (the regular inner condition; 0 for zero flux) on the inner face, T
+// per (j, k) from the shell transforms.  A thread owns one (j, k) column and
+// RROWS radial rows, with every load issued before the first store; the
+// neighbour rows come from cache (adjacent threads load them).
+constexpr int RROWS = 4;
+
+__global__ __launch_bounds__(256) void k_residual_phys(const double* __restrict__ rho, const double* __restrict__ phi,
+                                                       const double* __restrict__ tout,
+                                                       const double* __restrict__ tin, double* __restrict__ r,
+                                                       ResidualTables t, double four_pi_g, int nr, int nth,
+                                                       int nphi, double inv_dphi2, int gx)
+{
+    const int plane = nth * nphi;
+    const int chunk = blockIdx.x / gx;
+    const int e = (blockIdx.x - chunk * gx) * 256 + threadIdx.x;
+    if (e >= plane) return;
+    const int j = e / nphi, k = e - j * nphi;
+    const int ekp = k + 1 < nphi ? e + 1 : e + 1 - nphi;
+    const int ekm = k > 0 ? e - 1 : e - 1 + nphi;
+    const int ejp = j + 1 < nth ? e + nphi : e;       // pole faces: sigma = 0
+    const int ejm = j > 0 ? e - nphi : e;
+    const int i0 = chunk * RROWS;
+    auto row = [&](int i) { return size_t(i < 0 ? 0 : (i < nr ? i : nr - 1)) * plane; };
+    double c[RROWS + 2], kp[RROWS], km[RROWS], jp[RROWS], jm[RROWS], src[RROWS];
+#pragma unroll
+    for (int u = 0; u < RROWS + 2; ++u) c[u] = phi[row(i0 - 1 + u) + e];
+#pragma unroll
+    for (int u = 0; u < RROWS; ++u) {
+        const size_t b = row(i0 + u);
+        kp[u] = phi[b + ekp];
+        km[u] = phi[b + ekm];
+        jp[u] = phi[b + ejp];
+        jm[u] = phi[b + ejm];
+        src[u] = rho[b + e];
+    }
+    const double to = i0 + RROWS >= nr ? tout[e] : 0.0;
+    const double ti = (i0 == 0 && tin) ? tin[e] : 0.0;
+    const double sp = t.sig[j + 1], sm = t.sig[j], idm = 1.0 / t.dmu[j], sj = t.Sj[j] * inv_dphi2;
+#pragma unroll
+    for (int u = 0; u < RROWS; ++u) {
+        const int i = i0 + u;
+        if (i < nr) {
+            const double x = c[u + 1];
+            const double fo = i + 1 < nr ? t.alpha[i] * (c[u + 2] - x) : -to;
+            const double fi = i > 0 ? t.alpha[i - 1] * (x - c[u]) : ti;
+            const double Vi = t.V[i], Ri = t.VR[i] / Vi;
+            const double th = sp * (jp[u] - x) - sm * (x - jm[u]);
+            const double LP = (fo - fi) / Vi + Ri * (th * idm + sj * (kp[u] - 2.0 * x + km[u]));
+            r[size_t(i) * plane + e] = four_pi_g * src[u] - LP;
+        }
+    }
 }
 
 bool launch_proj_f32(const double* A, const float* B, double* C, int M, int K, int nphi, bool accum, hipStream_t s)
@@ -715,29 +907,35 @@ bool launch_proj_f32(const double* A, const float* B, double* C, int M, int K, i
 
 }  // namespace
 
+// Typed views of a plan's device tables.
+struct PlanTables {
+    const char* base;
+    explicit PlanTables(const spp_plan_s* p) : base(static_cast<const char*>(p->dev)) {}
+    const double* d(size_t off) const { return reinterpret_cast<const double*>(base + off); }
+    const float* f(size_t off) const { return reinterpret_cast<const float*>(base + off); }
+    const c64* c(size_t off) const { return reinterpret_cast<const c64*>(base + off); }
+};
+
 spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* phi, double G, void* ws,
-                                void* stream, hipEvent_t* ev)
+                                void* stream, hipEvent_t* ev, const unsigned* gate)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const char* base = static_cast<const char*>(p->dev);
-    const c64* tw = reinterpret_cast<const c64*>(base + p->lay.tw);
-    const double* W = reinterpret_cast<const double*>(base + p->lay.W);
-    const double* H = reinterpret_cast<const double*>(base + p->lay.H);
-    const double* lam = reinterpret_cast<const double*>(base + p->lay.lam);
-    const double* beta = reinterpret_cast<const double*>(base + p->lay.beta);
-    const double* alpha = reinterpret_cast<const double*>(base + p->lay.alpha);
-    const double* V = reinterpret_cast<const double*>(base + p->lay.V);
-    const double* VR = reinterpret_cast<const double*>(base + p->lay.VR);
-    const double* Wimg = reinterpret_cast<const double*>(base + p->lay.Wimg);
-    const double* Himg = reinterpret_cast<const double*>(base + p->lay.Himg);
-    const double* Wpar = reinterpret_cast<const double*>(base + p->lay.Wpar);
-    const double* Hpar = reinterpret_cast<const double*>(base + p->lay.Hpar);
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const c64* tw = T.c(L.tw);
+    const double *lam = T.d(L.lam), *beta = T.d(L.beta);
+    const radial::Coef cf{T.d(L.alpha), T.d(L.V), T.d(L.VR), p->nr, T.d(L.gamma)};
 
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
     const int nlines = nr * nth;
     const size_t field = spp_align256(size_t(nlines) * nphi * sizeof(double));
-    double* X = static_cast<double*>(ws);
-    double* Y = reinterpret_cast<double*>(static_cast<char*>(ws) + field);
+    // the status record, then the fields
+    auto* rec = static_cast<spp_status_record*>(ws);
+    char* fields = static_cast<char*>(ws) + SPP_STATUS_BYTES;
+    double* X = reinterpret_cast<double*>(fields);
+    double* Y = reinterpret_cast<double*>(fields + field);
+    // a gated solve (the mixed form's fallback) keeps the record it reports into
+    const FftExtra fwd{gate ? nullptr : rec, gate}, inv{rec, gate};
 
     // s~ scaled so that the inverse transform needs no 1/N: 4 pi G / N_phi
     const double scale = 4.0 * M_PI * G / nphi;
@@ -745,110 +943,163 @@ spp_status spp_launch_solve_f64(const spp_plan_s* p, const double* rho, double* 
         if (ev) (void)hipEventRecord(ev[k], s);
     };
     if (spp_plan_fused(p)) {
-        const double* Fimg = reinterpret_cast<const double*>(base + p->lay.Fimg);
-        const double* Iimg = reinterpret_cast<const double*>(base + p->lay.Iimg);
         mark(0);
-        if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s, true, nth))
+        if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s, true, nth, fwd))
             return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
         mark(1);
-        const double* Rimg = reinterpret_cast<const double*>(base + p->lay.Rimg);
         // the workspace's region after the spectral field is the sink of the
         // per-mode kernel's stores of padding rows and columns
         static_assert(modal::THREADS * sizeof(double) <= spp_modal_sink_bytes, "sink of one workgroup");
         // the kernel reaches the sink by 32-bit byte offsets from each unit's rows
         if (field + spp_modal_sink_bytes > (size_t(1) << 32))
             return spp_fail(SPP_ENOTSUP, "spp_solve: field too large for the fused kernel");
-        double* sink = reinterpret_cast<double*>(static_cast<char*>(ws) + field);
-        if (!launch_modal(X, Fimg, Iimg, Rimg, lam, beta, radial::Coef{alpha, V, VR, nr}, nr, nth, nphi, sink, s))
+        double* sink = reinterpret_cast<double*>(fields + field);
+        if (!launch_modal(X, T.d(L.Fimg), T.d(L.Iimg), T.d(L.Rimg), lam, beta, cf, nr, nth, nphi, sink, s, gate))
             return spp_fail(SPP_ENOTSUP, "spp_solve: grid outside the fused kernel's range");
         mark(2);
         mark(3);
         mark(4);
-        launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s, true, nth);
+        launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s, true, nth, inv);
         mark(5);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve: ") + hipGetErrorString(e));
         return SPP_OK;
     }
     mark(0);
-    if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s))
+    if (!launch_fft(nphi, true, rho, X, tw, scale, nlines, s, false, 0, fwd))
         return spp_fail(SPP_ENOTSUP, "spp_solve: unsupported nphi");
     mark(1);
     const dim3 pgrid((nth + PBN - 1) / PBN, (nr + PBM - 1) / PBM, nphi);
-    if (!launch_proj_par(X, Wpar, Y, nr, nth, nphi, true, p->par_rn, s) && !launch_proj(X, Wimg, Y, nr, nth, nphi, s))
-        hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, W, Y, nr, nth, nphi);
+    if (!launch_proj_par(X, T.d(L.Wpar), Y, nr, nth, nphi, true, p->par_rn, s, gate) &&
+        !launch_proj(X, T.d(L.Wimg), Y, nr, nth, nphi, s, gate))
+        hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, X, T.d(L.W), Y, nr, nth, nphi, gate);
     mark(2);
     const int nsys = nphi * nth;
-    if (!launch_radial_part(Y, lam, beta, alpha, V, VR, nr, nth, nphi, s))
-        hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, alpha, V, VR,
-                           nr, nth, nphi);
+    if (!launch_radial_part(Y, lam, beta, cf, nth, nphi, s, gate))
+        hipLaunchKernelGGL(k_radial, dim3((nsys + 255) / 256), dim3(256), 0, s, Y, X, lam, beta, cf.gamma, cf.alpha,
+                           cf.V, cf.VR, nr, nth, nphi, gate);
     mark(3);
-    if (!launch_proj_par(Y, Hpar, X, nr, nth, nphi, false, p->par_rn, s) && !launch_proj(Y, Himg, X, nr, nth, nphi, s))
-        hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, H, X, nr, nth, nphi);
+    if (!launch_proj_par(Y, T.d(L.Hpar), X, nr, nth, nphi, false, p->par_rn, s, gate) &&
+        !launch_proj(Y, T.d(L.Himg), X, nr, nth, nphi, s, gate))
+        hipLaunchKernelGGL(k_proj_f64, pgrid, dim3(256), 0, s, Y, T.d(L.H), X, nr, nth, nphi, gate);
     mark(4);
-    launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s);
+    launch_fft(nphi, false, X, phi, tw, 1.0, nlines, s, false, 0, inv);
     mark(5);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve: ") + hipGetErrorString(e));
     return SPP_OK;
 }
 
+namespace {
+
+// Workspace of the mixed form after the status record: s~, the accumulated
+// g, the residual, the projections' field, the outer and inner shell terms,
+// and the per-component maxima of the residuals [SPP_MAX_REFINE + 1][N_phi].
+struct MixedLayout {
+    size_t field, shell, St, Gf, Y, Z, ob, ib, part, total;
+    explicit MixedLayout(const spp_plan_s* p)
+    {
+        field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
+        shell = spp_align256(size_t(p->nphi) * p->nth * sizeof(double));
+        St = SPP_STATUS_BYTES;
+        Gf = St + field;
+        Y = Gf + field;
+        Z = Y + field;
+        ob = Z + field;
+        ib = ob + shell;
+        part = ib + shell;
+        total = part + spp_align256(size_t(SPP_MAX_REFINE + 1) * p->nphi * sizeof(unsigned long long));
+    }
+};
+
+// The outer-face term beta(A) g_N (and with the regular inner condition the
+// inner-face term gamma(A) g_1) of every Fourier component of the field F
+// [q][i][j] into ob (ib) [q][j]; c is a scratch of N_phi N_theta doubles.
+void launch_shell_terms(const spp_plan_s* p, const double* F, double* c, double* ob, double* ib, hipStream_t s)
+{
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    faceflux::launch_outer(F + size_t(nr - 1) * nth, size_t(nr) * nth, c, ob, T.d(L.W), T.d(L.H), T.d(L.beta),
+                           T.d(L.dmu), nth, nphi, s);
+    if (ib)
+        faceflux::launch_outer(F, size_t(nr) * nth, c, ib, T.d(L.W), T.d(L.H), T.d(L.gamma), T.d(L.dmu), nth,
+                               nphi, s);
+}
+
+}  // namespace
+
 size_t spp_mixed_workspace_bytes(const spp_plan_s* p)
 {
-    const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
-    return 4 * field + spp_align256(size_t(p->nphi) * p->nth * sizeof(double));
+    const MixedLayout M(p);
+    // the FP64 fallback solve runs in the same workspace
+    return std::max(M.total, spp_path_workspace_bytes(p, spp_plan_fused(p)));
 }
 
 // Mixed-precision solve (iterative refinement in Fourier space):
 //   s~ = FFT(4 pi G rho)                          FP64, once
 //   g  = H~ F^-1 W~ s~                            FP32-MFMA projections, FP64 radial
 //   repeat n_refine times:
-//     r = s~ - L g                                FP64 (local stencil + outer term)
+//     r = s~ - L g                                FP64 (local stencil + boundary terms)
 //     g += H~ F^-1 W~ r
 //   Phi = IFFT(g)                                 FP64, once
-spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refine, const double* rho,
-                                  double* phi, double G, void* ws, void* stream)
+// then the contraction check of k_refine_gate and, if a step did not contract
+// and fallback_fp64 is set, the FP64 solve, gated on the device.
+spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refine, int fallback_fp64,
+                                  const double* rho, double* phi, double G, void* ws, void* stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const char* base = static_cast<const char*>(p->dev);
-    auto tab = [&](size_t off) { return reinterpret_cast<const double*>(base + off); };
-    const c64* tw = reinterpret_cast<const c64*>(base + p->lay.tw);
-    const float* W32 = reinterpret_cast<const float*>(base + p->lay.Wimg32);
-    const float* H32 = reinterpret_cast<const float*>(base + p->lay.Himg32);
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const c64* tw = T.c(L.tw);
+    const float* W32 = T.f(L.Wimg32);
+    const float* H32 = T.f(L.Himg32);
+    const radial::Coef cf{T.d(L.alpha), T.d(L.V), T.d(L.VR), p->nr, T.d(L.gamma)};
 
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
     const int nlines = nr * nth;
-    const size_t field = spp_align256(size_t(nlines) * nphi * sizeof(double));
+    const MixedLayout M(p);
     char* w = static_cast<char*>(ws);
-    double* St = reinterpret_cast<double*>(w);              // s~ (kept for the residuals)
-    double* Gf = reinterpret_cast<double*>(w + field);      // accumulated g
-    double* Y = reinterpret_cast<double*>(w + 2 * field);   // residual
-    double* Z = reinterpret_cast<double*>(w + 3 * field);   // projections / radial solves
-    double* ob = reinterpret_cast<double*>(w + 4 * field);  // outer-shell boundary term
+    auto* rec = reinterpret_cast<spp_status_record*>(w);
+    double* St = reinterpret_cast<double*>(w + M.St);   // s~ (kept for the residuals)
+    double* Gf = reinterpret_cast<double*>(w + M.Gf);   // accumulated g
+    double* Y = reinterpret_cast<double*>(w + M.Y);     // residual
+    double* Z = reinterpret_cast<double*>(w + M.Z);     // projections / radial solves
+    double* ob = reinterpret_cast<double*>(w + M.ob);   // outer-shell term
+    double* ib = p->inner_regular ? reinterpret_cast<double*>(w + M.ib) : nullptr;
+    auto* part = reinterpret_cast<unsigned long long*>(w + M.part);
 
-    const ResidualTables rt{tab(p->lay.alpha), tab(p->lay.V), tab(p->lay.VR), tab(p->lay.sig), tab(p->lay.dmu),
-                            tab(p->lay.Sj), tab(p->lay.lamphi)};
+    const ResidualTables rt{T.d(L.alpha), T.d(L.V), T.d(L.VR), T.d(L.sig), T.d(L.dmu), T.d(L.Sj), T.d(L.lamphi)};
     const double scale = 4.0 * M_PI * G / nphi;
-    if (!launch_fft(nphi, true, rho, St, tw, scale, nlines, s))
+    if (!launch_fft(nphi, true, rho, St, tw, scale, nlines, s, false, 0, FftExtra{rec, nullptr}))
         return spp_fail(SPP_ENOTSUP, "spp_solve_mixed: unsupported nphi");
+    // per-component maxima start at zero (a fill kernel, capturable)
+    const size_t npart = size_t(n_refine + 1) * nphi;
+    hipLaunchKernelGGL(k_fill_u64, dim3((npart + 255) / 256), dim3(256), 0, s, part, npart);
+    const int rgx = std::min((nlines + 255) / 256, 8);
     for (int it = 0; it <= n_refine; ++it) {
         const double* src = St;
         if (it > 0) {
-            // outer-shell boundary term; Z is free until the projection below
-            faceflux::launch_outer(Gf + size_t(nr - 1) * nth, size_t(nr) * nth, Z, ob, tab(p->lay.W),
-                                   tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu), nth, nphi, s);
-            hipLaunchKernelGGL(k_residual, dim3((nlines + 255) / 256, nphi), dim3(256), 0, s, St, Gf, ob, Y, rt,
-                               nr, nth, nphi);
+            // boundary terms of the current g; Z is free until the projection below
+            launch_shell_terms(p, Gf, Z, ob, ib, s);
+            hipLaunchKernelGGL(k_residual, dim3(rgx, nphi), dim3(256), 0, s, St, Gf, ob, ib, Y, rt, nr, nth, nphi,
+                               part + size_t(it) * nphi, it == 1 ? part : nullptr);
             src = Y;
         }
         launch_proj_f32(src, W32, Z, nr, nth, nphi, false, s);
-        if (!launch_radial_part(Z, tab(p->lay.lam), tab(p->lay.beta), tab(p->lay.alpha), tab(p->lay.V),
-                                tab(p->lay.VR), nr, nth, nphi, s))
-            hipLaunchKernelGGL(k_radial, dim3((nphi * nth + 255) / 256), dim3(256), 0, s, Z, Y, tab(p->lay.lam),
-                               tab(p->lay.beta), tab(p->lay.alpha), tab(p->lay.V), tab(p->lay.VR), nr, nth, nphi);
+        if (!launch_radial_part(Z, T.d(L.lam), T.d(L.beta), cf, nth, nphi, s))
+            hipLaunchKernelGGL(k_radial, dim3((nphi * nth + 255) / 256), dim3(256), 0, s, Z, Y, T.d(L.lam),
+                               T.d(L.beta), cf.gamma, cf.alpha, cf.V, cf.VR, nr, nth, nphi, nullptr);
         launch_proj_f32(Z, H32, Gf, nr, nth, nphi, it > 0, s);
     }
-    launch_fft(nphi, false, Gf, phi, tw, 1.0, nlines, s);
+    launch_fft(nphi, false, Gf, phi, tw, 1.0, nlines, s, false, 0, FftExtra{rec, nullptr});
+    hipLaunchKernelGGL(k_refine_gate, dim3(1), dim3(256), 0, s, rec, part, nphi, n_refine, fallback_fp64);
+    if (fallback_fp64 && n_refine > 0) {
+        // the FP64 solve in the same workspace (its spectral fields overlay
+        // s~ and g), run only when the gate opened
+        const spp_status st = spp_launch_solve_f64(p, rho, phi, G, ws, stream, nullptr, &rec->fallback);
+        if (st != SPP_OK) return st;
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_solve_mixed: ") + hipGetErrorString(e));
     return SPP_OK;
@@ -858,35 +1109,75 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
 // term of Sec. 3.2 on the outermost shell, T = beta(A) Phi_shell, which acts
 // per angular eigenmode: the shell's Fourier components (forward FFT of its
 // N_theta lines), the two per-mode products of faceflux::launch_outer, and
-// the inverse FFT back to [j][k].  Workspace: two shell-sized buffers A, B
-// (A: spectrum, B: coefficients, A: boundary term per component, B: T).
+// the inverse FFT back to [j][k].  Workspace after its status record: two
+// shell-sized buffers A, B (A: spectrum, B: coefficients, A: boundary term per
+// component, B: T).
 spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double* fr, double* ft, double* fp,
                                   void* ws, void* stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const char* base = static_cast<const char*>(p->dev);
-    auto tab = [&](size_t off) { return reinterpret_cast<const double*>(base + off); };
-    const c64* tw = reinterpret_cast<const c64*>(base + p->lay.tw);
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const c64* tw = T.c(L.tw);
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
     const int plane = nth * nphi;
-    char* w = static_cast<char*>(ws);
+    char* w = static_cast<char*>(ws) + SPP_STATUS_BYTES;
     double* A = reinterpret_cast<double*>(w);
     double* B = reinterpret_cast<double*>(w + spp_align256(size_t(plane) * sizeof(double)));
 
     if (nth > faceflux::OUTER_NTH_MAX)
         return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: needs N_theta <= " + std::to_string(faceflux::OUTER_NTH_MAX));
+    if (p->inner_regular)
+        return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: the inner face flux of the regular inner condition is not "
+                                     "stored (grids with r_{1/2} > 0 need the zero-flux condition here)");
     if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, A, tw, 1.0 / nphi, nth, s))
         return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: unsupported nphi");
-    faceflux::launch_outer(A, size_t(nth), B, A, tab(p->lay.W), tab(p->lay.H), tab(p->lay.beta), tab(p->lay.dmu),
-                           nth, nphi, s);
+    faceflux::launch_outer(A, size_t(nth), B, A, T.d(L.W), T.d(L.H), T.d(L.beta), T.d(L.dmu), nth, nphi, s);
     launch_fft(nphi, false, A, B, tw, 1.0, nth, s);
-    const faceflux::Tables t{tab(p->lay.alpha), tab(p->lay.VR), tab(p->lay.sig), tab(p->lay.dmu), tab(p->lay.Sj)};
+    const faceflux::Tables t{T.d(L.alpha), T.d(L.VR), T.d(L.sig), T.d(L.dmu), T.d(L.Sj)};
     const int gx = (plane + faceflux::THREADS - 1) / faceflux::THREADS;
     const int chunks = (nr + faceflux::ROWS - 1) / faceflux::ROWS;
     hipLaunchKernelGGL(faceflux::k_face_fluxes, dim3(gx * chunks), dim3(faceflux::THREADS), 0, s, phi, B, fr, ft, fp,
                        t, nr, nth, nphi, 2.0 * M_PI / nphi, gx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_face_fluxes: ") + hipGetErrorString(e));
+    return SPP_OK;
+}
+
+// r = 4 pi G rho - L Phi (spp_residual).  The boundary terms of the outermost
+// (and, with the regular inner condition, the innermost) shell act per angular
+// eigenmode: shell FFT, the two per-mode products, inverse FFT, as for the
+// face fluxes.  Workspace after its status record: four shell buffers.
+spp_status spp_launch_residual(const spp_plan_s* p, const double* rho, const double* phi, double G, double* r,
+                               void* ws, void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const c64* tw = T.c(L.tw);
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    const int plane = nth * nphi;
+    const size_t sh = spp_align256(size_t(plane) * sizeof(double));
+    char* w = static_cast<char*>(ws) + SPP_STATUS_BYTES;
+    double *A = reinterpret_cast<double*>(w), *B = reinterpret_cast<double*>(w + sh);
+    double *C = reinterpret_cast<double*>(w + 2 * sh), *D = reinterpret_cast<double*>(w + 3 * sh);
+    if (nth > faceflux::OUTER_NTH_MAX)
+        return spp_fail(SPP_ENOTSUP, "spp_residual: needs N_theta <= " + std::to_string(faceflux::OUTER_NTH_MAX));
+    auto shell_term = [&](const double* shell, const double* coef, double* spec, double* out) {
+        launch_fft(nphi, true, shell, spec, tw, 1.0 / nphi, nth, s);
+        faceflux::launch_outer(spec, size_t(nth), out, spec, T.d(L.W), T.d(L.H), coef, T.d(L.dmu), nth, nphi, s);
+        launch_fft(nphi, false, spec, out, tw, 1.0, nth, s);
+    };
+    shell_term(phi + size_t(nr - 1) * plane, T.d(L.beta), A, B);
+    if (p->inner_regular) shell_term(phi, T.d(L.gamma), C, D);
+    const ResidualTables rt{T.d(L.alpha), T.d(L.V), T.d(L.VR), T.d(L.sig), T.d(L.dmu), T.d(L.Sj), T.d(L.lamphi)};
+    const int gx = (plane + 255) / 256;
+    const int chunks = (nr + RROWS - 1) / RROWS;
+    const double dphi = 2.0 * M_PI / nphi;
+    hipLaunchKernelGGL(k_residual_phys, dim3(gx * chunks), dim3(256), 0, s, rho, phi, B,
+                       p->inner_regular ? D : nullptr, r, rt, 4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_residual: ") + hipGetErrorString(e));
     return SPP_OK;
 }
 
@@ -904,8 +1195,8 @@ spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* str
     const char* base = static_cast<const char*>(p->dev);
     const double* Wimg = reinterpret_cast<const double*>(base + p->lay.Wimg);
     const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
-    const double* A = static_cast<const double*>(ws);
-    double* C = reinterpret_cast<double*>(static_cast<char*>(ws) + field);
+    const double* A = reinterpret_cast<const double*>(static_cast<char*>(ws) + SPP_STATUS_BYTES);
+    double* C = reinterpret_cast<double*>(static_cast<char*>(ws) + SPP_STATUS_BYTES + field);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return spp_fail(SPP_EDEVICE, "autotune: hipEventCreate");
     if (hipEventCreate(&e1) != hipSuccess) {

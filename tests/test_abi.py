@@ -35,7 +35,7 @@ def make_grid(r_if, th_if, nphi):
     r, rp = _f64(r_if)
     t, tp = _f64(th_if)
     g = _vp()
-    st = lib.spp_grid_create(r.size - 1, rp, t.size - 1, tp, nphi, ctypes.byref(g))
+    st = lib.spp_grid_create(r.size - 1, rp, t.size - 1, tp, nphi, 0, ctypes.byref(g))
     return st, g
 
 
@@ -158,10 +158,11 @@ def test_fused_path_range_guard():
 
 
 def test_workspace_holds_the_fused_kernels_store_sink():
-    """A fused plan's FP64 workspace covers both paths: the fused one (one
-    spectral field, then the per-mode kernel's store sink of one double per
-    thread of its 768-thread workgroup) and the staged one (two fields); a
-    staged-only plan needs the two fields."""
+    """A fused plan's FP64 workspace is the 256-byte status record followed by
+    what both paths need: the fused one (one spectral field, then the
+    per-mode kernel's store sink of one double per thread of its 768-thread
+    workgroup) and the staged one (two fields), at least four shells; a
+    staged-only plan needs the record and two fields."""
     def ws_bytes(r_if, th_if, nphi):
         st, g = make_grid(r_if, th_if, nphi)
         _check(st, "grid")
@@ -176,10 +177,10 @@ def test_workspace_holds_the_fused_kernels_store_sink():
         return wb.value, v.value
     field = 256                                   # 2 x 4 x 4 doubles, 256-byte aligned
     wb, path = ws_bytes(np.array([0.0, 1.0, 2.0]), synthetic.theta_interfaces(4), 4)
-    assert path == 2 and wb == max(field + 768 * 8, 2 * field)
+    assert path == 2 and wb == 256 + max(field + 768 * 8, 2 * field)
     th_ns = np.array([0.0, 0.5, 1.9, np.pi])      # not equator-symmetric: staged only
     wb, path = ws_bytes(np.array([0.0, 1.0, 2.0]), th_ns, 4)
-    assert path == 1 and wb == 2 * 256
+    assert path == 1 and wb == 256 + max(2 * 256, 4 * 256)
 
 
 def _host_kernels(r_if, th_if, nphi):
@@ -232,3 +233,49 @@ def test_binding_rejects_fields_on_the_wrong_device():
     for call in (lambda: p.solve(rho), lambda: p.solve_mixed(rho), lambda: p.face_fluxes(rho)):
         with pytest.raises(ValueError):
             call()
+
+
+def test_inner_condition_argument_and_path():
+    """spp_grid_create takes the inner condition: unknown values are refused;
+    the regular condition with r_{1/2} > 0 runs on the staged kernels (the
+    fused kernel's row records carry no inner-face term), while with
+    r_{1/2} = 0 (no inner face) it changes nothing."""
+    r0 = synthetic.uniform_interfaces(16, 0.5, 2.0)
+    r_zero = synthetic.uniform_interfaces(16, 0.0, 2.0)
+    th = synthetic.theta_interfaces(16)
+    r, rp = _f64(r0)
+    t, tp = _f64(th)
+    g = _vp()
+    assert lib.spp_grid_create(16, rp, 16, tp, 8, 7, ctypes.byref(g)) == -1
+
+    def path(r_if, inner):
+        rr, rrp = _f64(r_if)
+        gg = _vp()
+        _check(lib.spp_grid_create(rr.size - 1, rrp, 16, tp, 8, inner, ctypes.byref(gg)), "grid")
+        p = _vp()
+        _check(lib.spp_plan_create(gg, ctypes.byref(p)), "plan")
+        v = ctypes.c_int()
+        _check(lib.spp_plan_get_path(p, ctypes.byref(v)), "path")
+        lib.spp_plan_destroy(p)
+        lib.spp_grid_destroy(gg)
+        return v.value
+    FUSED, STAGED = 2, 1
+    assert path(r0, 0) == FUSED and path(r0, 1) == FUSED and path(r0, 2) == STAGED
+    assert path(r_zero, 2) == FUSED
+
+
+def test_residual_status_and_hook_argument_checks():
+    """spp_residual, spp_solve_status and the low-precision test hook reject
+    bad arguments before anything reaches the device."""
+    st, g = make_grid(np.array([0.0, 1.0, 2.0]), synthetic.theta_interfaces(4), 8)
+    p = _vp()
+    _check(lib.spp_plan_create(g, ctypes.byref(p)), "plan")
+    a, b, c, w = (ctypes.c_void_p(x) for x in (4096, 8192, 12288, 65536))
+    assert lib.spp_residual(p, a, b, 1.0, None, w, None) == -1
+    assert lib.spp_residual(None, a, b, 1.0, c, w, None) == -1
+    assert lib.spp_residual(p, a, b, 1.0, c, w, None) == -5          # not uploaded
+    assert lib.spp_solve_status(None, w, None, None) == -1
+    assert lib.spp_plan_scale_lowprec_basis(p, float("nan")) == -1
+    assert lib.spp_plan_scale_lowprec_basis(None, 2.0) == -1
+    lib.spp_plan_destroy(p)
+    lib.spp_grid_destroy(g)
