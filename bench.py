@@ -96,37 +96,58 @@ def measured_traffic(kernel, nr, nth, nphi):
     return round(t["bytes_per_launch"], 0)
 
 
-def cpu_baseline(case, phi_gpu, seconds):
-    """The FP64 oracle, as it stands, on the host cores (set-up excluded)."""
-    from oracle import spectral
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:      # threadpoolctl missing: report the visible cores
-        threads = os.cpu_count()
-    plan = spectral.Plan(case["r_if"], case["th_if"], case["nphi"])
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _timed_oracle_solves(plan, case, seconds, label):
     runs, t0 = 0, time.perf_counter()
     ref = None
     while True:
         ref = plan.solve(case["rho"], case["G"])
         runs += 1
         el = time.perf_counter() - t0
-        log(f"oracle solve {runs} done at {el:.1f} s")
+        log(f"oracle ({label}) solve {runs} done at {el:.1f} s")
         if el >= seconds:
             break
+    return ref, runs, el
+
+
+def cpu_baseline(case, phi_gpu, seconds, single_seconds):
+    """The FP64 oracle, as it stands, on the host cores (set-up excluded):
+    once with the BLAS/OpenMP pools at all host threads, once single-threaded."""
+    from oracle import spectral
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    plan = spectral.Plan(case["r_if"], case["th_if"], case["nphi"])
+    ref, runs, el = _timed_oracle_solves(plan, case, seconds, f"{threads} threads")
+    with threadpool_limits(limits=1):
+        _, runs1, el1 = _timed_oracle_solves(plan, case, single_seconds, "1 thread")
     err = float(np.max(np.abs(phi_gpu - ref)) / np.max(np.abs(ref)))
     return {"value": runs / el, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{runs} full FP64 oracle solves of the 550x128x256 stellar workload "
-                      f"({el:.1f} s wall, theta eigensystem set-up excluded)"}, err
+                      f"({el:.1f} s wall, theta eigensystem set-up excluded)",
+            "single_thread": {"value": runs1 / el1, "unit": "solves/s", "cores": 1,
+                              "sample": f"{runs1} solves of the same workload, BLAS/OpenMP limited to one "
+                                        f"thread ({el1:.1f} s wall)"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}, err
 
 
 def batched_leg(spp, torch, synthetic, steps):
     """64 right-hand sides on grids drawn from N_r x N_theta x N_phi in
     {128,256,550} x {32,64,128} x {64,128,256} (draw seed 3; sources as the
-    stellar workload with seeds 100..163), captured once into one HIP graph.
-    Plans are shared between entries of the same grid class and their
-    projection tiles autotuned.  Also times the same solves issued one after
-    another on one stream."""
+    stellar workload with seeds 100..163), one HIP graph per precision: FP64
+    (the right-hand sides of each grid class batched into one launch per
+    kernel, launch variants tuned per class at creation) and mixed (one
+    refinement).  Also times the same FP64 solves issued one after another on
+    one stream."""
     grids = synthetic.batch_grids()
     plans, rhos, phis = {}, [], []
     t0 = time.perf_counter()
@@ -134,21 +155,31 @@ def batched_leg(spp, torch, synthetic, steps):
         r_if, th_if, nphi = synthetic.stellar_grid(*g)
         if g not in plans:
             plans[g] = spp.Plan(r_if, th_if, nphi, device="cuda:0")
-            plans[g].autotune()
         rhos.append(torch.from_numpy(synthetic.stellar_density(r_if, th_if, nphi, 100 + k)).to("cuda:0"))
         phis.append(torch.empty_like(rhos[-1]))
     plist = [plans[g] for g in grids]
-    b = spp.Batch(plist, rhos, phis, [1.0] * len(grids))
     log(f"batched: {len(grids)} RHS, {len(plans)} plans, set-up {time.perf_counter() - t0:.1f} s")
     zones = sum(a * c * d for a, c, d in grids)
-    b.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+
+    def timed(b):
         b.launch()
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / steps
-    # the same solves one after another on the current stream (no graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.launch()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    out = {"rhs": len(grids), "plans": len(plans), "zones_per_batch": zones}
+    t0 = time.perf_counter()
+    b = spp.Batch(plist, rhos, phis, [1.0] * len(grids), autotune=True)
+    log(f"batched fp64: created and tuned in {time.perf_counter() - t0:.1f} s: {b.description}")
+    el = timed(b)
+    phi64 = [y.clone() for y in phis]
+    out["fp64"] = {"ms_per_batch": round(el * 1e3, 3), "rhs_per_s": round(len(grids) / el, 1),
+                   "gzones_per_s": round(zones / el / 1e9, 3), "tuning": b.description}
+    del b
+    # the same solves one after another on the current stream (no graph, no batching)
     for p, x, y in zip(plist, rhos, phis):
         p.solve(x, out=y)
     torch.cuda.synchronize()
@@ -158,19 +189,28 @@ def batched_leg(spp, torch, synthetic, steps):
             p.solve(x, out=y)
     torch.cuda.synchronize()
     el_seq = (time.perf_counter() - t0) / steps
-    log(f"batched: {el * 1e3:.2f} ms per batch (sequential {el_seq * 1e3:.2f} ms)")
-    return {"rhs": len(grids), "plans": len(plans), "zones_per_batch": zones,
-            "ms_per_batch": round(el * 1e3, 3), "rhs_per_s": round(len(grids) / el, 1),
-            "gzones_per_s": round(zones / el / 1e9, 3), "sequential_ms_per_batch": round(el_seq * 1e3, 3),
-            "graph_speedup_vs_sequential": round(el_seq / el, 3)}
+    out["fp64"]["sequential_ms_per_batch"] = round(el_seq * 1e3, 3)
+    out["fp64"]["speedup_vs_sequential"] = round(el_seq / el, 3)
+    log(f"batched fp64: {el * 1e3:.2f} ms per batch, {zones / el / 1e9:.1f} Gzones/s "
+        f"(sequential {el_seq * 1e3:.2f} ms)")
+    bm = spp.Batch(plist, rhos, phis, [1.0] * len(grids), precision="mixed_fp32", n_refine=1)
+    elm = timed(bm)
+    d = max((y - y0).abs().max().item() / y0.abs().max().item() for y, y0 in zip(phis, phi64))
+    out["mixed_fp32"] = {"n_refine": 1, "ms_per_batch": round(elm * 1e3, 3), "rhs_per_s": round(len(grids) / elm, 1),
+                         "gzones_per_s": round(zones / elm / 1e9, 3), "max_rel_diff_vs_fp64": d}
+    log(f"batched mixed: {elm * 1e3:.2f} ms per batch, diff vs FP64 {d:.2e}")
+    del bm
+    return out
 
 
 def serving_leg(spp, torch, synthetic, n_requests, rates):
     """Poisson arrivals (seed 4) of requests drawn uniformly from the grid
     classes (128,32,64), (256,64,128), (550,128,256) with off-centre point
     mass + Gaussian sources; plans resident, workspaces from an HBM pool,
-    8 concurrent slots.  First the saturated throughput (all requests queued
-    at once), then arrival rates at the given fractions of it."""
+    8 concurrent slots.  For each precision (FP64, and mixed: FP32 projections
+    with one FP64 refinement and the FP64 fallback armed): first the saturated
+    throughput (all requests queued at once), then arrival rates at the given
+    fractions of it."""
     classes = synthetic.SERVING_CLASSES
     plans, srcs, outs = [], [], []
     for c in classes:
@@ -180,13 +220,12 @@ def serving_leg(spp, torch, synthetic, n_requests, rates):
                      .to("cuda:0") for k in range(4)])
         outs.append([torch.empty_like(srcs[-1][0]) for _ in range(16)])
     n_slots = 8
-    pool = n_slots * max(p.workspace_bytes for p in plans)
     rng = np.random.default_rng(4)
     cls_of = rng.integers(0, len(classes), size=n_requests)
     gaps = rng.exponential(1.0, size=n_requests)
     zones = [a * b * c for a, b, c in classes]
 
-    def run(rate):
+    def run(rate, precision, pool):
         srv = spp.Server(plans, pool_bytes=pool, n_slots=n_slots)
         count = [0] * len(classes)
         t0 = srv.now() + 0.01
@@ -195,7 +234,8 @@ def serving_leg(spp, torch, synthetic, n_requests, rates):
             c = int(cls_of[k])
             j = count[c]
             count[c] += 1
-            srv.submit(c, srcs[c][j % 4], outs[c][j % 16], request_id=k, not_before=float(arrivals[k]))
+            srv.submit(c, srcs[c][j % 4], outs[c][j % 16], request_id=k, not_before=float(arrivals[k]),
+                       precision=precision, n_refine=1)
         srv.drain(300.0)
         done = srv.poll(n_requests + 16)
         srv.close()
@@ -206,16 +246,21 @@ def serving_leg(spp, torch, synthetic, n_requests, rates):
                 "solves_per_s": round(len(done) / span, 1), "gzones_per_s": round(z / span / 1e9, 3),
                 "p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4)}
 
-    run(None)   # warm-up
-    sat = run(None)
-    log(f"serving saturated: {sat['solves_per_s']} solves/s, p50 {sat['p50_ms']} ms, p99 {sat['p99_ms']} ms")
-    out = {"classes": [list(c) for c in classes], "n_slots": n_slots, "pool_bytes": pool,
-           "saturated": sat, "rates": []}
-    for f in rates:
-        r = run(f * sat["solves_per_s"])
-        r["fraction_of_saturation"] = f
-        out["rates"].append(r)
-        log(f"serving at {f:.2f} x sat: {r['solves_per_s']} solves/s, p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms")
+    out = {"classes": [list(c) for c in classes], "n_slots": n_slots}
+    for precision in ("fp64", "mixed_fp32"):
+        pool = n_slots * max(p.workspace_bytes_for(precision) for p in plans)
+        run(None, precision, pool)   # warm-up
+        sat = run(None, precision, pool)
+        log(f"serving {precision} saturated: {sat['solves_per_s']} solves/s, p50 {sat['p50_ms']} ms, "
+            f"p99 {sat['p99_ms']} ms")
+        leg = {"pool_bytes": pool, "saturated": sat, "rates": []}
+        for f in rates:
+            r = run(f * sat["solves_per_s"], precision, pool)
+            r["fraction_of_saturation"] = f
+            leg["rates"].append(r)
+            log(f"serving {precision} at {f:.2f} x sat: {r['solves_per_s']} solves/s, p50 {r['p50_ms']} ms, "
+                f"p99 {r['p99_ms']} ms")
+        out[precision] = leg
     return out
 
 
@@ -226,6 +271,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-single-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -418,7 +464,7 @@ def main():
         "serving": serving,
     }
     if not args.no_cpu_baseline:
-        cb, err = cpu_baseline(case, phi_np, args.cpu_seconds)
+        cb, err = cpu_baseline(case, phi_np, args.cpu_seconds, args.cpu_single_seconds)
         result["cpu_baseline"] = cb
         result["max_rel_err_vs_oracle"] = err
     result["paper_context"] = ("Table 1: 0.32 s (32 cores) to 0.08 s (1024 cores) per solve on the Magnus "

@@ -105,6 +105,9 @@ typedef struct {
                                 stream waits for it.  NULL: rho is already
                                 complete on the device at submission.  The event
                                 must stay valid until the completion is polled. */
+    int precision;           /* SPP_FP64 (spp_solve) or SPP_MIXED_FP32
+                                (spp_solve_mixed with the FP64 fallback)         */
+    int n_refine;            /* refinement steps of a mixed request (0..16)      */
 } spp_request;
 
 /* Completion record; times in seconds on the server's steady clock. */
@@ -348,31 +351,46 @@ spp_status spp_solve_profiled(spp_plan p, const double* rho_dev, double* phi_dev
 spp_status spp_autotune_projection(spp_plan p, void* workspace_dev, void* stream, int* chosen_rows);
 
 /*
- * Batched FP64 solves (many right-hand sides, grids of uneven size; plans
- * may be shared between entries).  Solve r is exactly spp_solve(plans[r],
- * rho_dev[r], phi_dev[r], G[r], ...) -- the same kernels, so each result is
- * bitwise the one of a lone solve.
- *   spp_batch_workspace_bytes: bytes of the one workspace the batch needs
- *     (the per-plan workspaces, each 256-byte aligned, back to back);
- *   spp_batch_create: validates every entry, then captures all solves into
- *     one HIP graph in which the solves are independent branches (up to 8
- *     concurrent chains).  Device pointers are fixed at creation.  The host
- *     arrays are copied; device buffers must outlive the batch;
+ * Batched solves: many right-hand sides on grids of uneven size (plans may be
+ * shared between entries).  Solve r is exactly spp_solve(plans[r], rho_dev[r],
+ * phi_dev[r], G[r], ...) -- or spp_solve_mixed with n_refine and the FP64
+ * fallback for prec = SPP_MIXED_FP32 -- in arithmetic, so each result is
+ * bitwise the one of a lone solve.  For FP64 the right-hand sides of a grid
+ * class on the fused path run batched: each kernel of the solve (folded
+ * forward FFT, per-mode kernel, folded inverse FFT) is one launch over all of
+ * them (or over each half, as the tuner chooses), so that small grids fill
+ * the device; other classes run one solve per right-hand side.  Everything is
+ * captured once into one HIP graph with up to 8 concurrent branches.
+ *   spp_batch_workspace_bytes: bytes of the one workspace the batch needs;
+ *   spp_batch_create: validates every entry, uploads the per-RHS pointer
+ *     tables into the workspace (synchronising `stream`), with autotune != 0
+ *     times each fused class's launch variants (the per-mode kernel's unit
+ *     order: XCD-paired or plain; one launch group or two concurrent halves)
+ *     on the real inputs, writing phi, and keeps the fastest; then captures
+ *     the graph.  Device pointers are fixed at creation; the host arrays are
+ *     copied; device buffers must outlive the batch;
  *   spp_batch_launch: replays the graph on `stream` (asynchronous);
- *   spp_solve_batched: create + launch + synchronise `stream` + destroy.
+ *   spp_batch_describe: the classes and the tuner's choices and timings, as
+ *     text (buf of len bytes, NUL-terminated; *needed may be NULL);
+ *   spp_batch_status: spp_solve_status of entry r (synchronises `stream`);
+ *   spp_solve_batched: create (no tuning) + launch + synchronise + destroy.
  * Errors: SPP_EINVAL (bad sizes/pointers/alignment, overlapping rho/phi),
- * SPP_ESTATE (plan not uploaded), SPP_EDEVICE (stream/graph calls).
+ * SPP_ENOTSUP (precision), SPP_ESTATE (plan not uploaded), SPP_EDEVICE
+ * (stream/graph calls).
  */
-spp_status spp_batch_workspace_bytes(int n, const spp_plan* plans, size_t* bytes);
+spp_status spp_batch_workspace_bytes(int n, const spp_plan* plans, spp_precision prec, size_t* bytes);
 spp_status spp_batch_create(int n, const spp_plan* plans, const double* const* rho_dev, double* const* phi_dev,
-                            const double* G, void* workspace_dev, spp_batch* out);
+                            const double* G, spp_precision prec, int n_refine, int autotune, void* workspace_dev,
+                            void* stream, spp_batch* out);
 spp_status spp_batch_launch(spp_batch b, void* stream);
+spp_status spp_batch_describe(spp_batch b, char* buf, size_t len, size_t* needed);
+spp_status spp_batch_status(spp_batch b, int r, void* stream, spp_solve_info* info);
 void spp_batch_destroy(spp_batch b);
 spp_status spp_solve_batched(int n, const spp_plan* plans, const double* const* rho_dev, double* const* phi_dev,
-                             const double* G, void* workspace_dev, void* stream);
+                             const double* G, spp_precision prec, int n_refine, void* workspace_dev, void* stream);
 
 /*
- * Serving loop with continuous batching (FP64 solves).
+ * Serving loop with continuous batching (FP64 and mixed-precision solves).
  *   spp_server_create: plans[0..n_plans) are the resident grid classes
  *     (uploaded; their eigenbases stay on the device); pool_dev/pool_bytes is
  *     caller-owned device memory from which each admitted request takes its
@@ -388,8 +406,10 @@ spp_status spp_solve_batched(int n, const spp_plan* plans, const double* const* 
  *     (SPP_ESTATE after timeout_s seconds).
  *   spp_server_now: current server clock.
  *   spp_server_destroy: drops queued requests, waits for running ones.
- * Each request runs exactly the kernels of spp_solve, so its result is
- * bitwise the same alone and in any mix.  rho/phi buffers must stay valid
+ * Each request runs exactly the kernels of spp_solve (or of spp_solve_mixed
+ * for a mixed request, whose workspace is the larger one of
+ * spp_plan_workspace_bytes), so its result is bitwise the same alone and in
+ * any mix.  rho/phi buffers must stay valid
  * until the request's completion has been polled.  The slot streams do not
  * wait on the caller's streams: rho must be complete at submission, or the
  * request names a ready_event to wait for.

@@ -58,24 +58,35 @@ class _SolveInfo(ctypes.Structure):
 
 lib.spp_solve_status.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_SolveInfo)]
 lib.spp_solve_status.restype = _c_int
+lib.spp_batch_status.argtypes = [_vp, _c_int, _vp, ctypes.POINTER(_SolveInfo)]
+lib.spp_batch_status.restype = _c_int
+
+
+def _info_dict(st, info):
+    d = {f: getattr(info, f) for f, _ in _SolveInfo._fields_}
+    d["status"] = STATUS_NAMES.get(st, st)
+    return d
 lib.spp_autotune_projection.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_c_int)]
 lib.spp_autotune_projection.restype = _c_int
 _vpp = ctypes.POINTER(_vp)
-lib.spp_batch_workspace_bytes.argtypes = [_c_int, _vpp, ctypes.POINTER(_c_size_t)]
+lib.spp_batch_workspace_bytes.argtypes = [_c_int, _vpp, _c_int, ctypes.POINTER(_c_size_t)]
 lib.spp_batch_workspace_bytes.restype = _c_int
-lib.spp_batch_create.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _vp, ctypes.POINTER(_vp)]
+lib.spp_batch_create.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _c_int, _c_int, _c_int, _vp, _vp, ctypes.POINTER(_vp)]
 lib.spp_batch_create.restype = _c_int
+lib.spp_batch_describe.argtypes = [_vp, ctypes.c_char_p, _c_size_t, ctypes.POINTER(_c_size_t)]
+lib.spp_batch_describe.restype = _c_int
 lib.spp_batch_launch.argtypes = [_vp, _vp]
 lib.spp_batch_launch.restype = _c_int
 lib.spp_batch_destroy.argtypes = [_vp]
 lib.spp_batch_destroy.restype = None
-lib.spp_solve_batched.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _vp, _vp]
+lib.spp_solve_batched.argtypes = [_c_int, _vpp, _vpp, _vpp, _dp, _c_int, _c_int, _vp, _vp]
 lib.spp_solve_batched.restype = _c_int
 
 
 class _Request(ctypes.Structure):
     _fields_ = [("plan_index", _c_int), ("rho_dev", _vp), ("phi_dev", _vp), ("G", _c_double),
-                ("request_id", ctypes.c_longlong), ("ready_event", _vp)]
+                ("request_id", ctypes.c_longlong), ("ready_event", _vp), ("precision", _c_int),
+                ("n_refine", _c_int)]
 
 
 class _Completion(ctypes.Structure):
@@ -378,13 +389,14 @@ class Plan:
 
 
 class Batch:
-    """Many FP64 solves captured once into one HIP graph (see spp_batch_create).
+    """Many solves captured once into one HIP graph (see spp_batch_create).
 
     ``plans[r]``, ``rhos[r]``, ``phis[r]`` and ``Gs[r]`` describe solve r; the
-    tensors are kept alive by the batch.  ``launch()`` replays all solves.
+    tensors are kept alive by the batch.  ``launch()`` replays all solves;
+    ``description`` names the classes and the tuner's choices.
     """
 
-    def __init__(self, plans, rhos, phis, Gs):
+    def __init__(self, plans, rhos, phis, Gs, precision="fp64", n_refine=1, autotune=True, stream=None):
         import torch
         n = len(plans)
         if not (len(rhos) == len(phis) == len(Gs) == n) or n == 0:
@@ -400,13 +412,30 @@ class Batch:
         self._rho = (_vp * n)(*[x.data_ptr() for x in rhos])
         self._phi = (_vp * n)(*[y.data_ptr() for y in phis])
         self._G = (ctypes.c_double * n)(*[float(g) for g in Gs])
+        prec = precision_codes[precision]
         wb = _c_size_t()
-        _check(lib.spp_batch_workspace_bytes(n, self._plans, ctypes.byref(wb)), "spp_batch_workspace_bytes")
+        _check(lib.spp_batch_workspace_bytes(n, self._plans, prec, ctypes.byref(wb)), "spp_batch_workspace_bytes")
         self.workspace = torch.empty(max(wb.value, 256), dtype=torch.uint8, device=plans[0].device)
         b = _vp()
-        _check(lib.spp_batch_create(n, self._plans, self._rho, self._phi, self._G,
-                                    _vp(self.workspace.data_ptr()), ctypes.byref(b)), "spp_batch_create")
+        _check(lib.spp_batch_create(n, self._plans, self._rho, self._phi, self._G, prec, int(n_refine),
+                                    int(bool(autotune)), _vp(self.workspace.data_ptr()), _stream_ptr(stream),
+                                    ctypes.byref(b)), "spp_batch_create")
         self._batch = b
+
+    @property
+    def description(self):
+        need = _c_size_t()
+        _check(lib.spp_batch_describe(self._batch, None, 0, ctypes.byref(need)), "spp_batch_describe")
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.spp_batch_describe(self._batch, buf, need.value, None), "spp_batch_describe")
+        return buf.value.decode()
+
+    def status(self, r, stream=None):
+        info = _SolveInfo()
+        st = lib.spp_batch_status(self._batch, int(r), _stream_ptr(stream), ctypes.byref(info))
+        if st not in (0, -6, -7):
+            _check(st, "spp_batch_status")
+        return _info_dict(st, info)
 
     def launch(self, stream=None):
         _check(lib.spp_batch_launch(self._batch, _stream_ptr(stream)), "spp_batch_launch")
@@ -446,10 +475,11 @@ class Server:
         _check(lib.spp_server_now(self._s, ctypes.byref(t)), "spp_server_now")
         return t.value
 
-    def submit(self, plan_index, rho, phi, G=1.0, request_id=0, not_before=0.0, stream=None):
-        """Queue one solve.  An event recorded on `stream` (default: the
-        current torch stream) after the work queued so far makes the slot
-        stream wait until rho is written."""
+    def submit(self, plan_index, rho, phi, G=1.0, request_id=0, not_before=0.0, stream=None,
+               precision="fp64", n_refine=1):
+        """Queue one solve (precision "fp64" or "mixed_fp32").  An event
+        recorded on `stream` (default: the current torch stream) after the work
+        queued so far makes the slot stream wait until rho is written."""
         import torch
         if not 0 <= int(plan_index) < len(self.plans):
             raise ValueError(f"plan_index must be in [0, {len(self.plans)})")
@@ -461,7 +491,7 @@ class Server:
         seq = self._seq
         self._seq += 1
         req = _Request(int(plan_index), _vp(rho.data_ptr()), _vp(phi.data_ptr()), float(G), seq,
-                       _vp(ready.cuda_event))
+                       _vp(ready.cuda_event), precision_codes[precision], int(n_refine))
         _check(lib.spp_server_submit(self._s, ctypes.byref(req), float(not_before)), "spp_server_submit")
         self._live[seq] = (int(request_id), rho, phi, ready)
 

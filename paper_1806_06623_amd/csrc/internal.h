@@ -95,6 +95,13 @@ spp_status spp_launch_residual(const spp_plan_s* p, const double* rho, const dou
 spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double* fr, double* ft, double* fp,
                                   void* ws, void* stream);
 
+// Batched FP64 solves of n right-hand sides of one fused-path plan, one launch
+// per kernel over all of them (solve.hip): region layout and size.
+size_t spp_class_batch_bytes(const spp_plan_s* p, int n);
+spp_status spp_launch_class_batch(const spp_plan_s* p, int n, const double* const* rho_tab,
+                                  double* const* phi_tab, const double* scale_tab, spp_status_record* recs,
+                                  double* X, double* sink, int paired, hipStream_t s);
+
 // Projection tile autotuner and launch-cache prewarm (solve.hip).
 spp_status spp_autotune_projection_impl(const spp_plan_s* p, void* ws, void* stream, int* chosen_rm);
 void spp_prewarm_launch_caches(const spp_plan_s* p);

@@ -203,10 +203,11 @@ __device__ __forceinline__ int lane_now()
 // workgroups, pair k = 8 (L / 16) + L % 8 has its q at L and its N_phi - q at
 // L + 8.  Pairs k < N_phi - 2 are (m = k/2 + 1, parity k % 2); the last two
 // hold the unpaired components q = 0 and q = N_phi/2 (one parity each at L
-// and L + 8).  Grids with N_phi < 8 keep the plain order.
-__device__ __forceinline__ void unit_of(int L, int nphi, int& q, int& par)
+// and L + 8).  Grids with N_phi < 8, and launches with paired == 0, keep the
+// plain order (q = L / 2, parity L % 2).
+__device__ __forceinline__ void unit_of(int L, int nphi, int paired, int& q, int& par)
 {
-    if (nphi < 8) {
+    if (nphi < 8 || !paired) {
         par = L & 1;
         q = L >> 1;
         return;
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
                                                    const double* __restrict__ lam,
                                                    const double* __restrict__ beta, radial::Coef tab, int nth,
                                                    int nphi, double* __restrict__ sink,
-                                                   const unsigned* __restrict__ gate)
+                                                   const unsigned* __restrict__ gate, size_t xstride, int paired)
 {
     if (spp_gate_closed(gate)) return;
     using Gm = Geo<RN>;
@@ -299,8 +300,16 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     __shared__ __attribute__((aligned(16))) double t_rec[(ROWS + P) * (RB / 8)];
     __shared__ double t_lam[16 * RN], t_bo[16 * RN];   // lambda_l, beta_l of this (m, parity)
 
+    // batched launch: RHS r owns the 2 N_phi workgroups from 2 N_phi r and the
+    // spectral field at r * xstride (xstride = 0: a single solve)
+    int L = blockIdx.x;
+    if (xstride) {
+        const int r = L / (2 * nphi);
+        L -= r * 2 * nphi;
+        X += r * xstride;
+    }
     int q, par;
-    unit_of(blockIdx.x, nphi, q, par);
+    unit_of(L, nphi, paired, q, par);
     const int m = q <= nphi / 2 ? q : nphi - q;
     const int nr = tab.nr, h = nth >> 1;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)

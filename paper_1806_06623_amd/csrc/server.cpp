@@ -68,6 +68,13 @@ private:
     std::map<size_t, size_t> free_;   // offset -> length
 };
 
+// Workspace bytes of one request.
+size_t request_workspace(const spp_plan_s* p, const spp_request& r)
+{
+    return spp_align256(r.precision == SPP_MIXED_FP32 ? spp_mixed_workspace_bytes(p)
+                                                     : spp_path_workspace_bytes(p, spp_plan_fused(p)));
+}
+
 struct Pending {
     spp_request req;
     double arrival;   // seconds on the server clock
@@ -147,9 +154,10 @@ void spp_server_s::run()
                 if (!free_slot) break;
                 const Pending job = queue.front();
                 const spp_plan_s* p = plans[job.req.plan_index];
-                // the workspace of the plan's current path (the fused path needs
-                // one spectral field, the staged path two)
-                const size_t need = spp_align256(spp_path_workspace_bytes(p, spp_plan_fused(p)));
+                // the workspace of the request (FP64: the plan's current path, the
+                // fused path needing one spectral field, the staged path two;
+                // mixed: the refinement's fields)
+                const size_t need = request_workspace(p, job.req);
                 size_t off = 0;
                 if (!alloc.alloc(need, &off)) break;   // wait for memory
                 queue.pop_front();
@@ -164,7 +172,10 @@ void spp_server_s::run()
                     hipStreamWaitEvent(free_slot->stream, static_cast<hipEvent_t>(job.req.ready_event), 0) !=
                         hipSuccess)
                     st = spp_fail(SPP_EDEVICE, "spp_server: hipStreamWaitEvent on the request's ready_event failed");
-                if (st == SPP_OK)
+                if (st == SPP_OK && job.req.precision == SPP_MIXED_FP32)
+                    st = spp_launch_solve_mixed(p, SPP_MIXED_FP32, job.req.n_refine, 1, job.req.rho_dev,
+                                                job.req.phi_dev, job.req.G, pool + off, free_slot->stream);
+                else if (st == SPP_OK)
                     st = spp_launch_solve_f64(p, job.req.rho_dev, job.req.phi_dev, job.req.G, pool + off,
                                               free_slot->stream);
                 if (st == SPP_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess)
@@ -245,7 +256,11 @@ extern "C" spp_status spp_server_submit(spp_server s, const spp_request* req, do
     const spp_plan_s* p = s->plans[req->plan_index];
     const spp_status st = spp_validate_solve("spp_server_submit", p, req->rho_dev, req->phi_dev, req->G, s->pool);
     if (st != SPP_OK) return st;
-    if (spp_align256(spp_path_workspace_bytes(p, spp_plan_fused(p))) > s->pool_bytes)
+    if (req->precision != SPP_FP64 && req->precision != SPP_MIXED_FP32)
+        return spp_fail(SPP_ENOTSUP, "spp_server_submit: precision must be SPP_FP64 or SPP_MIXED_FP32");
+    if (req->precision == SPP_MIXED_FP32 && (req->n_refine < 0 || req->n_refine > SPP_MAX_REFINE || p->proj_rn == 0))
+        return spp_fail(SPP_EINVAL, "spp_server_submit: mixed requests need n_refine in [0, 16] and N_theta <= 128");
+    if (request_workspace(p, *req) > s->pool_bytes)
         return spp_fail(SPP_ENOMEM, "spp_server_submit: request larger than the memory pool");
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) return spp_fail(SPP_ESTATE, "spp_server_submit: server is shutting down");

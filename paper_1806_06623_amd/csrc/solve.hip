@@ -49,10 +49,21 @@ template <int N, bool FOLD = false, bool PERSIST = true>
 __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(const double* __restrict__ rho, double* __restrict__ X,
                                                   const c64* __restrict__ tw_g, double scale, int nlines,
                                                   int nblocks, int nth, spp_status_record* __restrict__ reset,
-                                                  const unsigned* __restrict__ gate)
+                                                  const unsigned* __restrict__ gate, spp_batch_view bv)
 {
     if (spp_gate_closed(gate)) return;
-    spp_status_clear(reset);
+    // batched launch (one block per workgroup only): RHS r owns the nblocks
+    // workgroups from r * nblocks
+    int blk0 = blockIdx.x;
+    if (!PERSIST && bv.rho) {
+        const int r = blk0 / nblocks;
+        blk0 -= r * nblocks;
+        rho = bv.rho[r];
+        X += r * bv.xstride;
+        scale = bv.scale[r];
+        if (reset) reset += r;
+    }
+    spp_status_clear(reset, blk0 == 0);
     constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
     using S = FftShape<N, TH>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
@@ -96,7 +107,7 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_fwd(
     const int line = threadIdx.x / T, tid = threadIdx.x % T;
     const int l = threadIdx.x % JB, grp = threadIdx.x / JB;
     const size_t plane = size_t(nlines);
-    int blk = blockIdx.x;
+    int blk = blk0;
     if (blk < nblocks) prefetch(blk);
     for (; blk < nblocks; blk += gridDim.x) {
         if constexpr (FOLD) {
@@ -173,10 +184,18 @@ template <int N, bool FOLD = false, bool PERSIST = true>
 __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(const double* __restrict__ X, double* __restrict__ phi,
                                                   const c64* __restrict__ tw_g, int nlines, int nblocks, int nth,
                                                   spp_status_record* __restrict__ flag,
-                                                  const unsigned* __restrict__ gate)
+                                                  const unsigned* __restrict__ gate, spp_batch_view bv)
 {
     if (spp_gate_closed(gate)) return;
     bool bad = false;
+    int blk0 = blockIdx.x;
+    if (!PERSIST && bv.phi) {
+        const int r = blk0 / nblocks;
+        blk0 -= r * nblocks;
+        phi = bv.phi[r];
+        X += r * bv.xstride;
+        if (flag) flag += r;
+    }
     constexpr int TH = FOLD ? 512 : 256;         // 16 line pairs per block for N_phi = 256
     using S = FftShape<N, TH>;
     constexpr int N2 = S::N2, T = S::T, JB = S::JB, LS = LineStride<N2>::LS;
@@ -218,7 +237,7 @@ __global__ __launch_bounds__(FOLD ? 512 : 256, PERSIST ? 1 : 4) void k_rfft_inv(
         }
     };
 
-    int blk = blockIdx.x;
+    int blk = blk0;
     if (blk < nblocks) prefetch(blk);
     __syncthreads();   // twiddles
     for (; blk < nblocks; blk += gridDim.x) {
@@ -572,17 +591,19 @@ bool modal_variant(int nr, int nth, int* rn, int* T)
     return !(h % 2 != 0 || h > 64 || *T < 1 || *T > modalimg::TMAX);
 }
 
+// nrhs > 1: a batched launch over the spectral fields X + r * xstride.
 bool launch_modal(double* X, const double* Fimg, const double* Iimg, const double* Rimg, const double* lam,
                   const double* beta, const radial::Coef& cf, int nr, int nth, int nphi, double* sink,
-                  hipStream_t s, const unsigned* gate = nullptr)
+                  hipStream_t s, const unsigned* gate = nullptr, int nrhs = 1, size_t xstride = 0, int paired = 1)
 {
     int rn = 0, T = 0;
     if (!modal_variant(nr, nth, &rn, &T)) return false;
-    const dim3 grid(2 * nphi), block(modal::THREADS);   // one workgroup per (q, parity), see modal::unit_of
+    // one workgroup per (RHS, q, parity), see modal::unit_of
+    const dim3 grid(2 * nphi * nrhs), block(modal::THREADS);
 #define SPP_MODAL(RN, TT)                                                                                      \
     case RN * 4 + TT:                                                                                          \
         hipLaunchKernelGGL((modal::k_modal<RN, TT>), grid, block, 0, s, X, Fimg, Iimg, Rimg, lam, beta, cf, nth, nphi, \
-                           sink, gate);                                                                        \
+                           sink, gate, nrhs > 1 ? xstride : size_t(0), paired);                               \
         return true;
     switch (rn * 4 + T) {
         SPP_MODAL(1, 1)
@@ -625,6 +646,8 @@ int fft_resident(bool forward, bool fold)
 struct FftExtra {
     spp_status_record* rec = nullptr;
     const unsigned* gate = nullptr;
+    spp_batch_view bv{};       // batched launch over nrhs right-hand sides (folded FFTs only)
+    int nrhs = 1;
 };
 
 template <int N>
@@ -640,18 +663,18 @@ void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw,
     const int grid = (nblocks + per - 1) / per;
     if (forward) {
         if (fold)   // one block per workgroup (see k_rfft_fwd)
-            hipLaunchKernelGGL((k_rfft_fwd<N, true, false>), dim3(nblocks), dim3(512), 0, s, in, out, tw, scale,
-                               nlines, nblocks, nth, x.rec, x.gate);
+            hipLaunchKernelGGL((k_rfft_fwd<N, true, false>), dim3(nblocks * x.nrhs), dim3(512), 0, s, in, out, tw,
+                               scale, nlines, nblocks, nth, x.rec, x.gate, x.bv);
         else
             hipLaunchKernelGGL((k_rfft_fwd<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, scale, nlines,
-                               nblocks, nth, x.rec, x.gate);
+                               nblocks, nth, x.rec, x.gate, spp_batch_view{});
     } else {
         if (fold)
-            hipLaunchKernelGGL((k_rfft_inv<N, true, false>), dim3(nblocks), dim3(512), 0, s, in, out, tw, nlines,
-                               nblocks, nth, x.rec, x.gate);
+            hipLaunchKernelGGL((k_rfft_inv<N, true, false>), dim3(nblocks * x.nrhs), dim3(512), 0, s, in, out, tw,
+                               nlines, nblocks, nth, x.rec, x.gate, x.bv);
         else
             hipLaunchKernelGGL((k_rfft_inv<N, false>), dim3(grid), dim3(256), 0, s, in, out, tw, nlines, nblocks,
-                               nth, x.rec, x.gate);
+                               nth, x.rec, x.gate, spp_batch_view{});
     }
 }
 
@@ -1178,6 +1201,48 @@ spp_status spp_launch_residual(const spp_plan_s* p, const double* rho, const dou
                        p->inner_regular ? D : nullptr, r, rt, 4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_residual: ") + hipGetErrorString(e));
+    return SPP_OK;
+}
+
+// Batched FP64 solves of n right-hand sides of one fused-path plan: the
+// folded forward FFT, the per-mode kernel and the folded inverse FFT, each one
+// launch over all n (workgroups of RHS r consecutive).  recs: n status
+// records; X: n spectral fields back to back; sink: the per-mode kernel's
+// store sink, after the fields and within 4 GB of X (spp_class_batch_bytes
+// sizes records, fields and sink together); the tables (device) hold each
+// RHS's rho, phi and 4 pi G_r / N_phi.  paired: the per-mode kernel's
+// XCD-paired unit order.
+size_t spp_class_batch_bytes(const spp_plan_s* p, int n)
+{
+    const size_t field = spp_align256(size_t(p->nr) * p->nth * p->nphi * sizeof(double));
+    return size_t(n) * (SPP_STATUS_BYTES + field) + spp_modal_sink_bytes;
+}
+
+spp_status spp_launch_class_batch(const spp_plan_s* p, int n, const double* const* rho_tab,
+                                  double* const* phi_tab, const double* scale_tab, spp_status_record* recs,
+                                  double* X, double* sink, int paired, hipStream_t s)
+{
+    if (!spp_plan_fused(p)) return spp_fail(SPP_ENOTSUP, "batched launch: plan not on the fused path");
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi, nlines = nr * nth;
+    const size_t field = spp_align256(size_t(nlines) * nphi * sizeof(double));
+    // the per-mode kernel reaches the sink by 32-bit byte offsets from each unit's rows
+    const size_t reach = size_t(reinterpret_cast<char*>(sink) - reinterpret_cast<char*>(X)) + spp_modal_sink_bytes;
+    if (reinterpret_cast<char*>(sink) < reinterpret_cast<char*>(X) + size_t(n) * field || reach > (size_t(1) << 32))
+        return spp_fail(SPP_ENOTSUP, "batched launch: the store sink must follow the fields within 4 GB");
+    const size_t xstride = field / sizeof(double);
+    FftExtra fwd{recs, nullptr, spp_batch_view{rho_tab, nullptr, scale_tab, xstride}, n};
+    FftExtra inv{recs, nullptr, spp_batch_view{nullptr, phi_tab, nullptr, xstride}, n};
+    const radial::Coef cf{T.d(L.alpha), T.d(L.V), T.d(L.VR), nr, T.d(L.gamma)};
+    if (!launch_fft(nphi, true, nullptr, X, T.c(L.tw), 0.0, nlines, s, true, nth, fwd))
+        return spp_fail(SPP_ENOTSUP, "batched launch: unsupported nphi");
+    if (!launch_modal(X, T.d(L.Fimg), T.d(L.Iimg), T.d(L.Rimg), T.d(L.lam), T.d(L.beta), cf, nr, nth, nphi, sink, s,
+                      nullptr, n, xstride, paired))
+        return spp_fail(SPP_ENOTSUP, "batched launch: grid outside the fused kernel's range");
+    launch_fft(nphi, false, X, nullptr, T.c(L.tw), 1.0, nlines, s, true, nth, inv);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
     return SPP_OK;
 }
 

@@ -12,7 +12,7 @@
 #pragma once
 #include <cstddef>
 
-struct spp_status_record {
+struct alignas(256) spp_status_record {
     unsigned nonfinite;           // Phi holds a non-finite value
     unsigned fallback;            // gate of the FP64 fallback solve of the mixed form (1: run it)
     unsigned not_contracted;      // a refinement step of the mixed form did not contract
@@ -21,16 +21,29 @@ struct spp_status_record {
 };
 
 constexpr size_t SPP_STATUS_BYTES = 256;
-static_assert(sizeof(spp_status_record) <= SPP_STATUS_BYTES, "status record");
+static_assert(sizeof(spp_status_record) == SPP_STATUS_BYTES, "status record");
 constexpr int SPP_MAX_REFINE = 16;
 
 // A kernel launched with a gate returns at once unless the gate word is
 // non-zero; launched with NULL it always runs.
 __device__ __forceinline__ bool spp_gate_closed(const unsigned* gate) { return gate != nullptr && *gate == 0u; }
 
-// Zero the status record (first kernel of a solve, workgroup 0).
-__device__ __forceinline__ void spp_status_clear(spp_status_record* rec)
+// Zero the status record (first kernel of a solve, by the first workgroup of
+// the solve).
+__device__ __forceinline__ void spp_status_clear(spp_status_record* rec, bool first_block)
 {
-    if (rec && blockIdx.x == 0 && threadIdx.x < SPP_STATUS_BYTES / 8)
+    if (rec && first_block && threadIdx.x < SPP_STATUS_BYTES / 8)
         reinterpret_cast<unsigned long long*>(rec)[threadIdx.x] = 0ull;
 }
+
+// Several right-hand sides of one grid in one launch (batched solves): RHS r
+// reads rho[r], writes phi[r], scales by scale[r] and owns the spectral field
+// at r * xstride doubles and the status record at r (its workgroups are
+// consecutive).  With rho == nullptr (forward) / phi == nullptr (inverse) the
+// launch is a single solve.
+struct spp_batch_view {
+    const double* const* rho = nullptr;
+    double* const* phi = nullptr;
+    const double* scale = nullptr;
+    size_t xstride = 0;
+};

@@ -84,3 +84,41 @@ def test_scheduled_arrivals_are_respected():
     srv.close()
     assert c["t_arrival"] >= t0 + 0.05 - 1e-6
     assert c["t_admit"] >= c["t_arrival"]
+
+
+def test_mixed_and_fp64_requests_identical_alone_and_in_the_mix():
+    """Mixed-precision requests (FP32 projections, one refinement, FP64
+    fallback armed) interleaved with FP64 ones on the same classes: every
+    result is bitwise its lone solve of the same precision, and the mixed
+    ones are within 1e-10 of the oracle."""
+    spp, plans, grids = _setup()
+    rng = np.random.default_rng(44)
+    reqs = []
+    for k in range(40):
+        cls = int(rng.integers(0, len(CLASSES)))
+        prec = "mixed_fp32" if k % 2 else "fp64"
+        r_if, th_if, nphi = grids[cls]
+        rho = synthetic.serving_source(r_if, th_if, nphi, seed=2000 + k)
+        x = torch.from_numpy(rho).to("cuda")
+        reqs.append((cls, prec, x, torch.empty_like(x), rho))
+    alone = []
+    for cls, prec, x, _, _ in reqs:
+        p = plans[cls]
+        alone.append((p.solve_mixed(x, n_refine=1) if prec == "mixed_fp32" else p.solve(x)).clone())
+    torch.cuda.synchronize()
+    pool = 3 * max(p.workspace_bytes_for("mixed_fp32") for p in plans)
+    srv = spp.Server(plans, pool_bytes=pool, n_slots=4)
+    for k, (cls, prec, x, y, _) in enumerate(reqs):
+        srv.submit(cls, x, y, request_id=k, precision=prec, n_refine=1)
+    srv.drain(120.0)
+    done = srv.poll()
+    srv.close()
+    assert len(done) == len(reqs) and all(c["status"] == 0 for c in done)
+    for k, (cls, prec, x, y, rho) in enumerate(reqs):
+        assert torch.equal(y, alone[k]), f"request {k} ({prec}) differs in the mix"
+    cls, prec, x, y, rho = reqs[1]
+    r_if, th_if, nphi = grids[cls]
+    ref = spectral.solve(r_if, th_if, nphi, rho)
+    e = float(np.max(np.abs(y.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    print(f"[parity] served mixed request 1 class {CLASSES[cls]}: {e:.3e}", flush=True)
+    assert e <= 1e-10
