@@ -277,6 +277,38 @@ spp_status spp_face_fluxes(spp_plan p, const double* phi_dev, double* fr_dev, do
                            void* workspace_dev, void* stream);
 
 /*
+ * Momentum-conserving gravitational source term from Phi, enqueued on
+ * `stream`: the force on every cell, -integral of rho grad Phi over it, as the
+ * surface integral of the gravitational stress tensor
+ *   T = (grad Phi grad Phi - |grad Phi|^2 I / 2) / (4 pi G),  div T = rho grad Phi
+ * (a textbook identity, valid where Laplacian Phi = 4 pi G rho, which the
+ * solver's Phi satisfies in the flux form of Sec. 3.1 to rounding; the paper
+ * points to conservative source terms in Sec. 1 and Sec. 6 without giving
+ * one).  On each face the normal gradient is the flux form's difference
+ * quotient (outer face: the extrapolated derivative of Sec. 3.2), each
+ * tangential component the mean of the two adjacent cells' centred ones; the
+ * stress vector uses the exact integrals of the local unit vectors over the
+ * curved face.  Every face's vector is the same in both cells that share it,
+ * so interior faces cancel exactly: the grid's total momentum changes only
+ * through its outer boundary, and a spherically symmetric Phi gives zero net
+ * force (both to rounding).
+ *   phi_dev        device, [N_r][N_theta][N_phi] float64, read-only;
+ *   G              the gravitational constant (finite, non-zero);
+ *   fx/fy/fz_dev   device, same shape each, written: the Cartesian components
+ *                  (x along phi = 0 at theta = pi/2, z along theta = 0) of
+ *                  the force on the cell; divide by the cell volume for a
+ *                  force density;
+ *   workspace_dev  any FP64 workspace of the plan (two shells after its status
+ *                  record are used).
+ * Fields pairwise disjoint and disjoint from the workspace.  Errors
+ * (synchronous, nothing enqueued): SPP_EINVAL (NULL, misaligned, overlap,
+ * G), SPP_ESTATE (plan not uploaded), SPP_ENOTSUP (N_theta > 3840, or the
+ * regular inner condition with r_{1/2} > 0), SPP_EDEVICE (launch failure).
+ */
+spp_status spp_momentum_source(spp_plan p, const double* phi_dev, double G, double* fx_dev, double* fy_dev,
+                               double* fz_dev, void* workspace_dev, void* stream);
+
+/*
  * Workspace bytes of one solve in flight for a given precision (SPP_FP64: as
  * spp_plan_device_bytes; SPP_MIXED_FP32: the status record, four fields, two
  * shells and the residual maxima, at least the FP64 fallback's workspace).

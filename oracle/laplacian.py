@@ -17,21 +17,22 @@ from .geometry import grid_geometry
 from .spectral import inner_gamma, outer_beta, theta_eigensystem
 
 
-def _mode_function(geom, shell, coef_of_lambda):
+def _mode_function(geom, shell, coef_of_lambda, driver="stev"):
     """coef(A) shell: per Fourier mode m and theta eigenmode l, times coef(lambda)."""
     nphi = geom["nphi"]
     c = np.fft.rfft(shell, axis=1) / nphi
     out = np.empty_like(c)
     for m in range(c.shape[1]):
-        lam, H = theta_eigensystem(geom, m)
+        lam, H = theta_eigensystem(geom, m, driver)
         coef = (H.T * geom["dmu"][None, :]) @ c[:, m]
         out[:, m] = H @ (coef_of_lambda(lam) * coef)
     return np.fft.irfft(out, n=nphi, axis=1) * nphi
 
 
-def outer_flux(geom, shell):
-    """Outer-face term beta(A) Phi_shell for one (nth, nphi) shell."""
-    return _mode_function(geom, shell, lambda lam: outer_beta(geom, lam))
+def outer_flux(geom, shell, driver="stev"):
+    """Outer-face term beta(A) Phi_shell for one (nth, nphi) shell (`driver`:
+    the LAPACK tridiagonal eigensolver of the theta eigensystems)."""
+    return _mode_function(geom, shell, lambda lam: outer_beta(geom, lam), driver)
 
 
 def inner_flux(geom, shell, inner="zero_flux"):

@@ -45,6 +45,8 @@ lib.spp_plan_workspace_bytes.argtypes = [_vp, _c_int, ctypes.POINTER(_c_size_t)]
 lib.spp_plan_workspace_bytes.restype = _c_int
 lib.spp_solve_mixed.argtypes = [_vp, _c_int, _c_int, _c_int, _vp, _vp, _c_double, _vp, _vp]
 lib.spp_solve_mixed.restype = _c_int
+lib.spp_momentum_source.argtypes = [_vp, _vp, _c_double, _vp, _vp, _vp, _vp, _vp]
+lib.spp_momentum_source.restype = _c_int
 lib.spp_residual.argtypes = [_vp, _vp, _vp, _c_double, _vp, _vp, _vp]
 lib.spp_residual.restype = _c_int
 lib.spp_plan_scale_lowprec_basis.argtypes = [_vp, _c_double]
@@ -330,6 +332,23 @@ class Plan:
         d = {f: getattr(info, f) for f, _ in _SolveInfo._fields_}
         d["status"] = STATUS_NAMES.get(st, st)
         return d
+
+    def momentum_source(self, phi, G=1.0, out=None, workspace=None, stream=None):
+        """Force on every cell from the gravitational stress tensor
+        (spp_momentum_source): three float64 tensors (Fx, Fy, Fz) of Phi's
+        shape."""
+        import torch
+        self._check_field(phi, "phi")
+        if out is None:
+            out = tuple(torch.empty_like(phi) for _ in range(3))
+        for t, name in zip(out, ("out[0]", "out[1]", "out[2]")):
+            self._check_field(t, name)
+        ws = self.workspace if workspace is None else workspace
+        self._check_workspace(ws, self.workspace_bytes)
+        _check(lib.spp_momentum_source(self._plan, _vp(phi.data_ptr()), float(G), _vp(out[0].data_ptr()),
+                                       _vp(out[1].data_ptr()), _vp(out[2].data_ptr()), _vp(ws.data_ptr()),
+                                       _stream_ptr(stream)), "spp_momentum_source")
+        return out
 
     def residual(self, rho, phi, G=1.0, out=None, workspace=None, stream=None):
         """r = 4 pi G rho - L Phi in FP64 (spp_residual)."""

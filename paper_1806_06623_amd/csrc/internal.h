@@ -42,6 +42,7 @@ struct spp_plan_layout {
     size_t dmu = 0;     // cos theta_{j-1/2} - cos theta_{j+1/2}, [N_theta]
     size_t Sj = 0;      // S_j, [N_theta]
     size_t lamphi = 0;  // lambda_{phi,m}, [M]
+    size_t mom = 0;     // factors of the momentum source's face integrals (spp_mom_layout)
     size_t total = 0;
 };
 
@@ -49,7 +50,7 @@ struct spp_plan_s {
     int nr = 0, nth = 0, nphi = 0, nm = 0;   // nm = N_phi/2 + 1 azimuthal modes
     std::vector<double> r_if, th_if;
     // host tables (float64), layouts as in spp_plan_layout
-    std::vector<double> tw, W, H, lam, beta, gamma, alpha, V, VR, Wimg, Himg, sig, dmu, Sj, lamphi;
+    std::vector<double> tw, W, H, lam, beta, gamma, alpha, V, VR, Wimg, Himg, sig, dmu, Sj, lamphi, mom;
     bool inner_regular = false;                // regular inner condition with r_{1/2} > 0
     std::vector<float> Wimg32, Himg32;
     std::vector<double> Ue, Uo, Wpar, Hpar;   // half-size even/odd eigenvectors and their images
@@ -84,6 +85,12 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision prec, int n
 // Workspace of the mixed-precision solve: the status record, four fields, two
 // shells and the residual maxima (and at least the FP64 fallback's workspace).
 size_t spp_mixed_workspace_bytes(const spp_plan_s* p);
+
+// Device entry of the momentum source (solve.hip): the force on every cell
+// from the gravitational stress tensor; the workspace needs two shells after
+// its status record.
+spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G, double* fx, double* fy, double* fz,
+                               void* ws, void* stream);
 
 // Device entry of the FP64 residual r = 4 pi G rho - L Phi (solve.hip); the
 // workspace needs four shells after its status record.
@@ -128,6 +135,22 @@ bool spp_tridiag_eigen(int n, std::vector<double>& d, std::vector<double> e, std
 inline bool spp_plan_fused(const spp_plan_s* p) { return p->fused_ok && p->path.load() != SPP_PATH_STAGED; }
 
 constexpr size_t spp_align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Offsets (in doubles) of the momentum source's tables inside the plan's `mom`
+// vector, in the order of momentum::Tables.
+struct spp_mom_layout {
+    size_t R2, ring, invr, invdr, is2, isc, is, ic, dth, invsdp, invdthc, fst, fct, jc, js, cp1, sp1, total;
+    spp_mom_layout(int nr, int nth, int nphi)
+    {
+        size_t o = 0;
+        auto take = [&](size_t n) { const size_t r = o; o += n; return r; };
+        R2 = take(nr + 1); ring = take(nr); invr = take(nr); invdr = take(nr + 1);
+        is2 = take(nth); isc = take(nth); is = take(nth); ic = take(nth); dth = take(nth); invsdp = take(nth);
+        invdthc = take(nth + 1); fst = take(nth + 1); fct = take(nth + 1);
+        jc = take(nphi); js = take(nphi); cp1 = take(nphi); sp1 = take(nphi);
+        total = o;
+    }
+};
 
 // Workspace bytes after the spectral field of a fused FP64 solve that the
 // per-mode kernel uses as the sink of its stores of padding rows and columns:

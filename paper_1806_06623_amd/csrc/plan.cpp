@@ -396,6 +396,41 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             p->lamphi[m] = -sm * sm;
         }
 
+        // momentum source: the factors of the exact face integrals of the
+        // local unit vectors and of the face difference quotients
+        {
+            const spp_mom_layout M(nr, nth, nphi);
+            p->mom.assign(M.total, 0.0);
+            double* q = p->mom.data();
+            for (int i = 0; i <= nr; ++i) q[M.R2 + i] = g->r_if[i] * g->r_if[i];
+            for (int i = 0; i < nr; ++i) {
+                q[M.ring + i] = 0.5 * (g->r_if[i + 1] * g->r_if[i + 1] - g->r_if[i] * g->r_if[i]);
+                q[M.invr + i] = 1.0 / G.r[i];
+            }
+            for (int i = 1; i < nr; ++i) q[M.invdr + i] = 1.0 / (G.r[i] - G.r[i - 1]);
+            for (int j = 0; j < nth; ++j) {
+                const double a = g->th_if[j], b = g->th_if[j + 1];
+                q[M.is2 + j] = 0.5 * (b - a) - 0.25 * (std::sin(2 * b) - std::sin(2 * a));
+                q[M.isc + j] = 0.5 * (std::sin(b) * std::sin(b) - std::sin(a) * std::sin(a));
+                q[M.is + j] = std::cos(a) - std::cos(b);
+                q[M.ic + j] = std::sin(b) - std::sin(a);
+                q[M.dth + j] = b - a;
+                q[M.invsdp + j] = 1.0 / (std::sin(G.th[j]) * dphi);
+            }
+            for (int j = 1; j < nth; ++j) {
+                q[M.invdthc + j] = 1.0 / (G.th[j] - G.th[j - 1]);
+                q[M.fst + j] = std::sin(g->th_if[j]);
+            }
+            for (int j = 0; j <= nth; ++j) q[M.fct + j] = std::cos(g->th_if[j]);
+            for (int k = 0; k < nphi; ++k) {
+                const double c = 2.0 * M_PI * k / nphi, d = 2.0 * M_PI * (k + 1) / nphi;
+                q[M.jc + k] = std::sin(d) - std::sin(c);
+                q[M.js + k] = std::cos(c) - std::cos(d);
+                q[M.cp1 + k] = std::cos(d);
+                q[M.sp1 + k] = std::sin(d);
+            }
+        }
+
         // LDS images of W_m and H_m for the projection kernel (N_theta <= 128)
         if (nth <= 128) {
             const int rn = projimg::rn_for(nth);
@@ -504,6 +539,7 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.dmu = take(p->dmu.size());
         L.Sj = take(p->Sj.size());
         L.lamphi = take(p->lamphi.size());
+        L.mom = take(p->mom.size());
         L.total = off;
         // the larger of what either path needs (spp_plan_set_path may switch
         // paths after the caller has sized its workspace)
@@ -607,6 +643,7 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.dmu, p->dmu);
     put(p->lay.Sj, p->Sj);
     put(p->lay.lamphi, p->lamphi);
+    put(p->lay.mom, p->mom);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(plan_dev, img.data(), img.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -715,6 +752,30 @@ extern "C" spp_status spp_solve_status(spp_plan p, const void* workspace_dev, vo
     if (rec.not_contracted && !rec.fallback)
         return spp_fail(SPP_ENOCONV, "spp_solve_status: the refinement did not contract (FP64 fallback disabled)");
     return SPP_OK;
+}
+
+extern "C" spp_status spp_momentum_source(spp_plan p, const double* phi_dev, double G, double* fx_dev,
+                                          double* fy_dev, double* fz_dev, void* workspace_dev, void* stream)
+{
+    if (!p || !phi_dev || !fx_dev || !fy_dev || !fz_dev || !workspace_dev)
+        return spp_fail(SPP_EINVAL, "spp_momentum_source: NULL pointer");
+    if (!p->dev) return spp_fail(SPP_ESTATE, "spp_momentum_source: plan not uploaded");
+    if (reinterpret_cast<uintptr_t>(workspace_dev) & 255)
+        return spp_fail(SPP_EINVAL, "spp_momentum_source: workspace must be 256-byte aligned");
+    if (!std::isfinite(G) || G == 0.0) return spp_fail(SPP_EINVAL, "spp_momentum_source: G must be finite and non-zero");
+    const size_t n = size_t(p->nr) * p->nth * p->nphi * sizeof(double);
+    const size_t wsn = SPP_STATUS_BYTES + 2 * spp_align256(size_t(p->nth) * p->nphi * sizeof(double));
+    const char* b[4] = {reinterpret_cast<const char*>(phi_dev), reinterpret_cast<const char*>(fx_dev),
+                        reinterpret_cast<const char*>(fy_dev), reinterpret_cast<const char*>(fz_dev)};
+    const char* wsb = static_cast<const char*>(workspace_dev);
+    for (int x = 0; x < 4; ++x) {
+        for (int y = x + 1; y < 4; ++y)
+            if (b[x] < b[y] + n && b[y] < b[x] + n)
+                return spp_fail(SPP_EINVAL, "spp_momentum_source: phi and the three force fields must not overlap");
+        if (b[x] < wsb + wsn && wsb < b[x] + n)
+            return spp_fail(SPP_EINVAL, "spp_momentum_source: the workspace must not overlap a field");
+    }
+    return spp_launch_momentum(p, phi_dev, G, fx_dev, fy_dev, fz_dev, workspace_dev, stream);
 }
 
 extern "C" spp_status spp_residual(spp_plan p, const double* rho_dev, const double* phi_dev, double G,

@@ -21,6 +21,7 @@
 #include "fluxes.hip.h"
 #include "internal.h"
 #include "modal.hip.h"
+#include "momentum.hip.h"
 #include "proj.hip.h"
 #include "radial.hip.h"
 #include "status.h"
@@ -1164,6 +1165,45 @@ spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double
                        t, nr, nth, nphi, 2.0 * M_PI / nphi, gx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_face_fluxes: ") + hipGetErrorString(e));
+    return SPP_OK;
+}
+
+// Force on every cell from the gravitational stress tensor (momentum.hip.h).
+// The outer face's normal gradient, -beta(A) Phi_shell / r_o^2, comes from the
+// shell transforms as for the face fluxes.  Workspace after its status
+// record: two shell buffers.
+spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G, double* fx, double* fy, double* fz,
+                               void* ws, void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const PlanTables T(p);
+    const auto& L = p->lay;
+    const c64* tw = T.c(L.tw);
+    const int nr = p->nr, nth = p->nth, nphi = p->nphi;
+    const int plane = nth * nphi;
+    char* w = static_cast<char*>(ws) + SPP_STATUS_BYTES;
+    double* A = reinterpret_cast<double*>(w);
+    double* B = reinterpret_cast<double*>(w + spp_align256(size_t(plane) * sizeof(double)));
+    if (nth > faceflux::OUTER_NTH_MAX)
+        return spp_fail(SPP_ENOTSUP, "spp_momentum_source: needs N_theta <= " + std::to_string(faceflux::OUTER_NTH_MAX));
+    if (p->inner_regular)
+        return spp_fail(SPP_ENOTSUP, "spp_momentum_source: grids with the regular inner condition are not supported");
+    if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, A, tw, 1.0 / nphi, nth, s))
+        return spp_fail(SPP_ENOTSUP, "spp_momentum_source: unsupported nphi");
+    faceflux::launch_outer(A, size_t(nth), B, A, T.d(L.W), T.d(L.H), T.d(L.beta), T.d(L.dmu), nth, nphi, s);
+    launch_fft(nphi, false, A, B, tw, 1.0, nth, s);
+    const spp_mom_layout M(nr, nth, nphi);
+    const double* q = T.d(L.mom);
+    const momentum::Tables t{q + M.R2, q + M.ring, q + M.invr, q + M.invdr, q + M.is2, q + M.isc, q + M.is,
+                             q + M.ic, q + M.dth, q + M.invsdp, q + M.invdthc, q + M.fst, q + M.fct, q + M.jc,
+                             q + M.js, q + M.cp1, q + M.sp1};
+    const int gx = (plane + momentum::THREADS - 1) / momentum::THREADS;
+    const int chunks = (nr + momentum::MROWS - 1) / momentum::MROWS;
+    const double ro = p->r_if[nr];
+    hipLaunchKernelGGL(momentum::k_momentum, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, B, fx, fy, fz, t, nr,
+                       nth, nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_momentum_source: ") + hipGetErrorString(e));
     return SPP_OK;
 }
 

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import analytic, dense, fluxes, geometry, laplacian, spectral
+from oracle import analytic, dense, fluxes, geometry, laplacian, momentum, spectral
 import synthetic
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -550,3 +550,169 @@ def test_ellipsoid_radial_jump_matches_paper():
     r_if = np.concatenate((base, base[-1] + 1.5 * dr * np.arange(1, nr - i15 + 1)))
     e = _ellipsoid_error(r_if, nth, nphi, tuple(g["axes"]))
     assert abs(e / g["max_rel_err_jump_at_1p5"] - 1.0) <= g["tolerance_fraction"], e
+
+
+# ------------------------------------------------------ momentum source
+def _unit_vectors(th, ph):
+    st, ct, sp, cp = np.sin(th), np.cos(th), np.sin(ph), np.cos(ph)
+    return (np.stack([st * cp, st * sp, ct], -1), np.stack([ct * cp, ct * sp, -st], -1),
+            np.stack([-sp, cp, 0.0 * st], -1))
+
+
+def test_momentum_face_integrals_match_quadrature():
+    """The exact face integrals of e_r, e_theta, e_phi against a 24 x 24
+    Gauss-Legendre rule over each curved face (brute force, no closed form)."""
+    rng = np.random.default_rng(8)
+    r_if, th_if, nphi = random_r_if(rng, 3, 0.5), random_th_if(rng, 4), 5
+    fv = momentum._face_vectors(r_if, th_if, nphi)
+    x, w = np.polynomial.legendre.leggauss(24)
+    ph_if = 2 * np.pi * np.arange(nphi + 1) / nphi
+
+    def quad(lo1, hi1, lo2, hi2, f):
+        u = 0.5 * (hi1 + lo1) + 0.5 * (hi1 - lo1) * x
+        v = 0.5 * (hi2 + lo2) + 0.5 * (hi2 - lo2) * x
+        U, Vv = np.meshgrid(u, v, indexing="ij")
+        W = np.outer(w, w) * 0.25 * (hi1 - lo1) * (hi2 - lo2)
+        return np.einsum("ab,abc->c", W, f(U, Vv))
+
+    i, j, k = 2, 1, 3
+    R = r_if[i]                                   # r-face i - 1/2, column (j, k)
+    er = quad(th_if[j], th_if[j + 1], ph_if[k], ph_if[k + 1],
+              lambda t, p: _unit_vectors(t, p)[0] * (R * R * np.sin(t))[..., None])
+    et = quad(th_if[j], th_if[j + 1], ph_if[k], ph_if[k + 1],
+              lambda t, p: _unit_vectors(t, p)[1] * (R * R * np.sin(t))[..., None])
+    ep = quad(th_if[j], th_if[j + 1], ph_if[k], ph_if[k + 1],
+              lambda t, p: _unit_vectors(t, p)[2] * (R * R * np.sin(t))[..., None])
+    for got, want in ((fv["r"]["N"][i, j, k], er), (fv["r"]["T1"][i, j, k], et), (fv["r"]["T2"][i, j, k], ep)):
+        assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
+    TH = th_if[j]                                 # theta-face j - 1/2, row i, column k
+    f = lambda idx: quad(r_if[i], r_if[i + 1], ph_if[k], ph_if[k + 1],
+                         lambda r, p: _unit_vectors(TH + 0 * r, p)[idx] * (r * np.sin(TH))[..., None])
+    for got, idx in ((fv["t"]["N"][i, j, k], 1), (fv["t"]["T1"][i, j, k], 0), (fv["t"]["T2"][i, j, k], 2)):
+        want = f(idx)
+        assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
+    PH = ph_if[k + 1]                             # phi-face k + 1/2, row i, column j
+    g = lambda idx: quad(r_if[i], r_if[i + 1], th_if[j], th_if[j + 1],
+                         lambda r, t: _unit_vectors(t, PH + 0 * t)[idx] * r[..., None])
+    for got, idx in ((fv["p"]["N"][i, j, k], 2), (fv["p"]["T1"][i, j, k], 0), (fv["p"]["T2"][i, j, k], 1)):
+        want = g(idx)
+        assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
+
+
+def test_momentum_cell_surfaces_close_and_interior_faces_cancel():
+    """Each cell's six integrated normals sum to zero (a closed surface), and
+    for any field the cell forces add up to the boundary faces' terms alone:
+    interior faces cancel (total momentum conserved to rounding)."""
+    rng = np.random.default_rng(9)
+    r_if, th_if, nphi = random_r_if(rng, 5, 0.4), random_th_if(rng, 6), 8
+    fv = momentum._face_vectors(r_if, th_if, nphi)
+    N = fv
+    close = ((N["r"]["N"][1:] - N["r"]["N"][:-1]) + (N["t"]["N"][:, 1:] - N["t"]["N"][:, :-1])
+             + (N["p"]["N"] - np.roll(N["p"]["N"], 1, axis=2)))
+    assert np.max(np.abs(close)) < 1e-14 * np.max(np.abs(N["r"]["N"]))
+    P = rng.standard_normal((5, 6, nphi))
+    F, Sr = momentum.cell_forces(r_if, th_if, nphi, P, G=0.8)
+    total = F.sum(axis=(0, 1, 2))
+    boundary = -(Sr[-1].sum(axis=(0, 1)) - Sr[0].sum(axis=(0, 1)))
+    assert np.max(np.abs(total - boundary)) < 1e-14 * np.abs(F).sum()
+
+
+def test_momentum_spherical_source_has_zero_net_force_and_radial_cell_forces():
+    """A spherically symmetric Phi (the discrete Gauss-law solution): every
+    shell's forces sum to zero and each cell's force is along the integral of
+    e_r over its solid angle, pointing inwards."""
+    nr, nth, nphi = 48, 12, 16
+    r_if, th_if = synthetic.stellar_r_interfaces(nr), synthetic.skewed_theta(nth)
+    r = 0.5 * (r_if[:-1] + r_if[1:])
+    rho_r = (1 + (r / 20.0) ** 2) ** -1.5
+    phi = np.broadcast_to(analytic.spherical_discrete_potential(r_if, 4 * np.pi * rho_r)[:, None, None],
+                          (nr, nth, nphi)).copy()
+    F, _ = momentum.cell_forces(r_if, th_if, nphi, phi)
+    scale = np.abs(F).max()
+    assert np.max(np.abs(F.sum(axis=(1, 2)))) < 1e-13 * scale * nth * nphi
+    dirs = momentum._face_vectors(r_if, th_if, nphi)["r"]["N"][-1]     # int e_r over the outer sphere's cells
+    dirs = dirs / np.linalg.norm(dirs, axis=-1, keepdims=True)
+    along = np.einsum("ijkc,jkc->ijk", F, dirs)
+    perp = F - along[..., None] * dirs[None]
+    assert np.max(np.abs(perp)) < 1e-12 * scale
+    assert np.all(along < 0)
+
+
+def _momentum_convergence(n):
+    from scipy.special import erf
+    nr, nth, nphi = 2 * n, n, 2 * n
+    r_if, th_if = synthetic.uniform_interfaces(nr, 0.0, 2.0), synthetic.theta_interfaces(nth)
+    sig, c = 0.2, (0.6, np.pi / 2, np.pi)
+    rho = synthetic.gaussian_blob(r_if, th_if, nphi, c, sig)
+    phi = spectral.solve(r_if, th_if, nphi, rho)
+    F, _ = momentum.cell_forces(r_if, th_if, nphi, phi)
+    r, t, p = geometry.cell_centres(r_if, th_if, nphi)
+    R, T, Pp = np.meshgrid(r, t, p, indexing="ij")
+    X = np.stack([R * np.sin(T) * np.cos(Pp), R * np.sin(T) * np.sin(Pp), R * np.cos(T)], -1)
+    C = np.array([c[0] * np.sin(c[1]) * np.cos(c[2]), c[0] * np.sin(c[1]) * np.sin(c[2]), c[0] * np.cos(c[1])])
+    D = X - C
+    d = np.linalg.norm(D, axis=-1)
+    u = d / (np.sqrt(2) * sig)
+    dphidd = (2 * np.pi * sig ** 2) ** 1.5 * (erf(u) / d ** 2 - np.sqrt(2 / np.pi) / sig * np.exp(-u * u) / d)
+    grad = dphidd[..., None] * D / d[..., None]          # gradient of -G M erf(u) / d (G = 1)
+    dV = geometry.cell_volumes(r_if, th_if, nphi)[:, :, None] * np.ones(nphi)
+    want = -(rho * dV)[..., None] * grad
+    return float(np.max(np.abs(F - want)) / np.max(np.abs(want)))
+
+
+def test_momentum_source_converges_to_minus_rho_grad_phi():
+    """The cell forces of the exact discrete potential of a Gaussian mass
+    converge at second order to -rho grad Phi delta V of the continuum
+    potential -G M erf(d / (sqrt 2 sigma)) / d."""
+    e = [_momentum_convergence(n) for n in (16, 32, 64)]
+    assert e[2] < 5e-3
+    assert 3.5 < e[0] / e[1] < 4.5 and 3.5 < e[1] / e[2] < 4.5
+
+
+def test_momentum_pins_catch_planted_mistakes(monkeypatch):
+    """Slips in the stress vector or the face integrals fail the pins above:
+    the sign of the shear terms, the factor 1/2, and a face's integrated
+    normal off by 1 %."""
+    orig_vec = momentum._face_vectors
+
+    def scaled_normals(r_if, th_if, nphi):      # the r-faces' integrated normals off by 1 %
+        out = orig_vec(r_if, th_if, nphi)
+        out["r"]["N"] = out["r"]["N"] * 1.01
+        return out
+
+    assert _momentum_convergence(16) < 0.06
+    for slip in ("shear", "half"):
+        def bad(r_if, th_if, nphi, Phi, G=1.0, _slip=slip):
+            gr, gt, gp = momentum.face_gradients(r_if, th_if, nphi, Phi)
+            sign = -1.0 if _slip == "shear" else 1.0
+            half = 1.0 if _slip == "half" else 0.5
+            cr = 0.5 * (gr[:-1] + gr[1:])
+            ct = 0.5 * (gt[:, :-1] + gt[:, 1:])
+            cp = 0.5 * (gp + np.roll(gp, 1, axis=2))
+
+            def pad_mean(x, axis):
+                x0, x1 = np.take(x, [0], axis=axis), np.take(x, [-1], axis=axis)
+                mid = 0.5 * (np.take(x, range(0, x.shape[axis] - 1), axis=axis)
+                             + np.take(x, range(1, x.shape[axis]), axis=axis))
+                return np.concatenate((x0, mid, x1), axis=axis)
+            fv = momentum._face_vectors(r_if, th_if, nphi)
+            k4 = 1.0 / (4.0 * np.pi * G)
+
+            def stress(gn, g1, g2, f):
+                return k4 * ((half * (gn * gn - g1 * g1 - g2 * g2))[..., None] * f["N"]
+                             + sign * (gn * g1)[..., None] * f["T1"] + sign * (gn * g2)[..., None] * f["T2"])
+            Sr = stress(gr, pad_mean(ct, 0), pad_mean(cp, 0), fv["r"])
+            St = stress(gt, pad_mean(cr, 1), pad_mean(cp, 1), fv["t"])
+            Sp = stress(gp, 0.5 * (cr + np.roll(cr, -1, axis=2)), 0.5 * (ct + np.roll(ct, -1, axis=2)), fv["p"])
+            F = -((Sr[1:] - Sr[:-1]) + (St[:, 1:] - St[:, :-1]) + (Sp - np.roll(Sp, 1, axis=2)))
+            return F, Sr
+        monkeypatch.setattr(momentum, "cell_forces", bad)
+        assert _momentum_convergence(16) > 0.1, slip
+        monkeypatch.undo()
+    monkeypatch.setattr(momentum, "_face_vectors", scaled_normals)
+    rng = np.random.default_rng(9)
+    r_if, th_if, nphi = random_r_if(rng, 5, 0.4), random_th_if(rng, 6), 8
+    fv = momentum._face_vectors(r_if, th_if, nphi)
+    close = ((fv["r"]["N"][1:] - fv["r"]["N"][:-1]) + (fv["t"]["N"][:, 1:] - fv["t"]["N"][:, :-1])
+             + (fv["p"]["N"] - np.roll(fv["p"]["N"], 1, axis=2)))
+    assert np.max(np.abs(close)) > 1e-6 * np.max(np.abs(fv["r"]["N"]))
