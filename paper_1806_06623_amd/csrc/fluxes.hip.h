@@ -23,6 +23,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "xcd.h"
+
 namespace faceflux {
 
 constexpr int THREADS = 256;
@@ -38,20 +40,10 @@ struct Tables {
 };
 
 // One-dimensional grid of gx * ceil(N_r / ROWS) workgroups, gx =
-// ceil(N_theta N_phi / THREADS) blocks of the (j, k) plane per chunk of rows.
-// Workgroups are dispatched to the 8 XCDs (each with its own L2) in turn, so
-// with gx a multiple of 8 the plane blocks are permuted to give the
-// workgroups of one XCD a contiguous range of the plane: the theta
-// neighbours a block reads (the next row of the plane) are then loaded by a
-// block on the same XCD, into the same L2, instead of being fetched again.
-// `outer` holds the boundary term T[j][k] of the outermost shell.  Row
-// indices past N_r - 1 are clamped for the loads (those values are never
-// used) and skipped for the stores.
-__device__ __forceinline__ int plane_block(int x, int gx)
-{
-    return gx % 8 == 0 ? (x % 8) * (gx / 8) + x / 8 : x;
-}
-
+// ceil(N_theta N_phi / THREADS) blocks of the (j, k) plane per chunk of rows,
+// in the XCD-aware order of spp_plane_block.  `outer` holds the boundary
+// term T[j][k] of the outermost shell.  Row indices past N_r - 1 are clamped
+// for the loads (those values are never used) and skipped for the stores.
 __global__ __launch_bounds__(THREADS) void k_face_fluxes(const double* __restrict__ phi,
                                                          const double* __restrict__ outer,
                                                          double* __restrict__ fr, double* __restrict__ ft,
@@ -60,7 +52,7 @@ __global__ __launch_bounds__(THREADS) void k_face_fluxes(const double* __restric
 {
     const int plane = nth * nphi;
     const int chunk = blockIdx.x / gx;
-    const int e = plane_block(blockIdx.x - chunk * gx, gx) * THREADS + threadIdx.x;
+    const int e = spp_plane_block(blockIdx.x - chunk * gx, gx) * THREADS + threadIdx.x;
     if (e >= plane) return;
     const int j = e / nphi;
     const int k = e - j * nphi;

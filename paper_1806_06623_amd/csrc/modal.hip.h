@@ -365,6 +365,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             store_part<HALF_E, HALF_E>(Bs, second, tid0);
             __syncthreads();
         }
+
         // issue priority falls as a wave gets ahead, so that the three waves of
         // a SIMD share the matrix pipe evenly and finish the product together
         // (with equal priorities the oldest wave runs ahead and the radial
@@ -613,19 +614,20 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     auto round = [&](auto rc) __attribute__((always_inline)) {
         constexpr int r = decltype(rc)::value;
         MODAL_PHASE_FENCE();
+        // the inverse image goes into the forward image's LDS (free since the
+        // end of round 0) by direct copies from quartet 2, issued at the start
+        // of round 1 so that their memory latency (a few microseconds: the
+        // image comes from HBM for one of the two workgroups that share it)
+        // overlaps the round's passes; the barrier that ends the round waits
+        // for their completion, and the inverse phase starts without a load
+        if constexpr (r == 1 && RN >= 2) {
+            if (quartet == 2) image_dma<ELEMS, 4>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS, w - 8, lane_now());
+        }
         if constexpr (r >= 1 && r <= RN) {
             if (quartet == (r - 1) % 3) solve(std::integral_constant<int, r - 1>{});
         }
         if constexpr (r >= 2) pass2(std::integral_constant<int, r - 2>{});
         if constexpr (r < RN) pass1(std::integral_constant<int, r>{});
-        // the inverse image goes into the forward image's LDS (free since the
-        // end of round 0) by direct copies from quartet 2, issued at the end of
-        // round 2: the barrier waits for their completion, but in round 2
-        // quartet 2 would wait there for the solving quartet 1 anyway; the
-        // inverse phase then starts without a load
-        if constexpr (r == 2 && RN >= 2) {
-            if (quartet == 2) image_dma<ELEMS, 4>(Bs, Iimg + (size_t(m) * 2 + par) * ELEMS, w - 8, lane_now());
-        }
         if constexpr (r <= RN) __syncthreads();
     };
     static_for<0, RN + 2>(round);

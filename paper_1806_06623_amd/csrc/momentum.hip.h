@@ -20,12 +20,18 @@
 // that share it, with floating-point contraction off, so the two values are
 // bitwise equal and interior faces cancel exactly in the grid's total.
 //
-// Thread per (j, k) column and MROWS radial rows; the 3 x 3 (j, k)
-// neighbourhoods of three consecutive rows are held in registers and rolled
-// down the rows.  HBM-bound: Phi once (neighbours from cache), three fields
-// written.
+// Thread per (j, k) column and MROWS radial rows (plane blocks in the
+// XCD-aware order of spp_plane_block).  Per row a thread forms every centred
+// component it needs once (radial ones at the five columns of its plus
+// stencil, theta and phi ones at the three cells along each direction), the
+// radial quotients of a face are carried from one row to the next, and the
+// r-face between two rows is evaluated once; the theta- and phi-faces are
+// evaluated by both cells that share them.  Phi is read once from HBM (the
+// neighbours' values from cache), three fields are written.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "xcd.h"
 
 namespace momentum {
 
@@ -61,20 +67,62 @@ struct V3 {
 
 #pragma clang fp contract(off)
 
-// The integrated stress vector of one face.
-__device__ __forceinline__ V3 stress(double gn, double g1, double g2, V3 N, V3 T1, V3 T2, double k4)
+// The scalars of a face's stress vector: with s = k4 times the face's radial
+// factor (r^2 of an r-face, the ring factor of a theta- or phi-face),
+//   a = s (G_n^2 - G_t1^2 - G_t2^2) / 2,  b = s G_n G_t1,  c = s G_n G_t2,
+// so that the integrated vector is a N + b T1 + c T2 (N, T1, T2 the angular
+// parts of the face's unit-vector integrals).
+struct Abc {
+    double a, b, c;
+};
+
+__device__ __forceinline__ Abc scalars(double gn, double g1, double g2, double s, double hs)
 {
-    const double a = 0.5 * (gn * gn - g1 * g1 - g2 * g2), b = gn * g1, c = gn * g2;
-    return V3{k4 * (a * N.x + b * T1.x + c * T2.x), k4 * (a * N.y + b * T1.y + c * T2.y),
-              k4 * (a * N.z + b * T1.z + c * T2.z)};
+    const double sg = s * gn;
+    return Abc{hs * ((gn * gn - g1 * g1) - g2 * g2), sg * g1, sg * g2};
+}
+
+// r-face of column (j, k): N = (S2 jc, S2 js, SC dphi), T1 = (SC jc, SC js,
+// -S2 dphi), T2 = (-SN js, SN jc, 0) with S2, SC, SN the integrals of sin^2,
+// sin cos and sin over the cell's theta range and jc, js the differences of
+// sin and cos phi over its phi range, collected as
+//   x = jc u - js v,  y = js u + jc v,  z = dphi (a SC - b S2),  u = a S2 + b SC,  v = c SN.
+__device__ __forceinline__ V3 rvec(const Abc& q, double S2, double SC, double SN, double jc, double js, double dphi)
+{
+    const double u = q.a * S2 + q.b * SC, v = q.c * SN;
+    return V3{jc * u - js * v, js * u + jc * v, dphi * (q.a * SC - q.b * S2)};
+}
+
+// theta-face at theta_f (st = sin, ct = cos): N = (st ct jc, st ct js,
+// -st^2 dphi), T1 = (st^2 jc, st^2 js, st ct dphi), T2 = (-st js, st jc, 0).
+__device__ __forceinline__ V3 tvec(const Abc& q, double sct, double ss, double st, double jc, double js, double dphi)
+{
+    const double u = q.a * sct + q.b * ss, v = q.c * st;
+    return V3{jc * u - js * v, js * u + jc * v, dphi * (q.b * sct - q.a * ss)};
+}
+
+// phi-face at phi_f (c1 = cos, s1 = sin) of a cell with theta width D and
+// sin / cos integrals SN, CS: N = (-D s1, D c1, 0), T1 = (SN c1, SN s1, CS),
+// T2 = (CS c1, CS s1, -SN).
+__device__ __forceinline__ V3 pvec(const Abc& q, double D, double SN, double CS, double c1, double s1)
+{
+    const double w = q.b * SN + q.c * CS, ad = q.a * D;
+    return V3{c1 * w - s1 * ad, s1 * w + c1 * ad, q.b * CS - q.c * SN};
 }
 
 __device__ __forceinline__ double avg(double a, double b) { return 0.5 * (a + b); }
 
-// 3 x 3 neighbourhood of one row: v[dj + 1][dk + 1] = Phi(i, j + dj, k + dk)
-// (theta neighbours clamped at the poles, phi periodic).
-struct Patch {
-    double v[3][3];
+// Centred gradient components of the cells a thread needs in one row i:
+// radial ones at the five columns of the plus stencil (0 own, 1 j-1, 2 j+1,
+// 3 k-1, 4 k+1), theta ones at (j, k-1), (j, k), (j, k+1), phi ones at
+// (j-1, k), (j, k), (j+1, k); the own column's face quotients in theta and
+// phi (the normal components of its theta- and phi-faces) and the radial
+// quotients of the upper face i + 1/2 at the five columns (the lower face's
+// for row i + 1).
+struct RowComps {
+    double cr[5], ct[3], cp[3];
+    double gtl, gth, gpl, gph;
+    double grh[5];
 };
 
 __global__ __launch_bounds__(THREADS) void k_momentum(const double* __restrict__ phi, const double* __restrict__ tout,
@@ -84,159 +132,159 @@ __global__ __launch_bounds__(THREADS) void k_momentum(const double* __restrict__
 {
     const int plane = nth * nphi;
     const int chunk = blockIdx.x / gx;
-    const int e = (blockIdx.x - chunk * gx) * THREADS + threadIdx.x;
+    const int e = spp_plane_block(blockIdx.x - chunk * gx, gx) * THREADS + threadIdx.x;
     if (e >= plane) return;
     const int j = e / nphi, k = e - j * nphi;
     const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < nth ? j + 1 : nth - 1;
     const int km = k > 0 ? k - 1 : nphi - 1, kp = k + 1 < nphi ? k + 1 : 0;
-    const int cols[3] = {jm * nphi, j * nphi, jp * nphi};
-    const int kk[3] = {km, k, kp};
+    // 32-bit byte offsets of the 3 x 3 patch within a row of the field (a row
+    // of at most 2^29 elements)
+    unsigned off[3][3];
+    {
+        const unsigned rowo[3] = {unsigned(jm * nphi), unsigned(j * nphi), unsigned(jp * nphi)};
+        const unsigned colo[3] = {unsigned(km), unsigned(k), unsigned(kp)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) off[a][b] = (rowo[a] + colo[b]) * 8u;   // bytes
+    }
     const int i0 = chunk * MROWS;
     const int i1 = i0 + MROWS < nr ? i0 + MROWS : nr;
+    // plus-stencil column c as (theta row a, phi column b) of the 3 x 3 patch
+    constexpr int PA[5] = {1, 0, 2, 1, 1}, PB[5] = {1, 1, 1, 0, 2};
 
-    auto load = [&](int i, Patch& p) {
-        const size_t base = size_t(i < 0 ? 0 : (i < nr ? i : nr - 1)) * plane;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) p.v[a][b] = phi[base + cols[a] + kk[b]];
-    };
-    // the outer face's normal gradient at the five columns of the plus stencil
-    double go[3][3] = {};
-    if (i1 == nr) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) go[a][b] = -tout[cols[a] + kk[b]] * inv_ro2;
-    }
+    // the per-column factors, read once (the table pointers may alias the
+    // outputs as far as the compiler knows)
+    const double jck = t.jc[k], jsk = t.js[k];
+    const double S2 = t.is2[j], SC = t.isc[j], SN = t.is[j], CS = t.ic[j], D = t.dth[j];
+    const double stl = t.fst[j], sth = t.fst[j + 1];
+    const double sctl = stl * t.fct[j], ssl = stl * stl, scth = sth * t.fct[j + 1], ssh = sth * sth;
+    const double c1l = t.cp1[km], s1l = t.sp1[km], c1h = t.cp1[k], s1h = t.sp1[k];
+    const double qtl = t.invdthc[j], qth = t.invdthc[j + 1];
+    const double qp[3] = {t.invsdp[jm], t.invsdp[j], t.invsdp[jp]};
 
-    // centred components of cell (i, j + a - 1, k + b - 1)
-    auto ct_of = [&](const Patch& p, int i, int a, int b) {
-        // theta faces j' - 1/2 and j' + 1/2 of column j' = j + a - 1; the
-        // neighbour beyond the patch is only needed for a = 0 / 2, which the
-        // force never asks for
-        const int jj = a == 0 ? jm : a == 1 ? j : jp;
-        const double lo = (p.v[a][b] - p.v[a > 0 ? a - 1 : 0][b]) * t.invr[i] * t.invdthc[jj];
-        const double hi = (p.v[a < 2 ? a + 1 : 2][b] - p.v[a][b]) * t.invr[i] * t.invdthc[jj + 1];
-        return avg(lo, hi);
-    };
-    auto cp_of = [&](const Patch& p, int i, int a, int b) {
-        const int jj = a == 0 ? jm : a == 1 ? j : jp;
-        const double lo = (p.v[a][b] - p.v[a][b > 0 ? b - 1 : 0]) * t.invr[i] * t.invsdp[jj];
-        const double hi = (p.v[a][b < 2 ? b + 1 : 2] - p.v[a][b]) * t.invr[i] * t.invsdp[jj];
-        return avg(lo, hi);
-    };
-    // radial centred component of cell i at column (a, b): the rows below and
-    // above; the inner face's quotient is 0 (invdr[0] = 0), the outer face's
-    // comes from go
-    auto cr_of = [&](const Patch& below, const Patch& here, const Patch& above, int i, int a, int b) {
-        const double lo = (here.v[a][b] - below.v[a][b]) * t.invdr[i];
-        const double hi = i + 1 < nr ? (above.v[a][b] - here.v[a][b]) * t.invdr[i + 1] : go[a][b];
-        return avg(lo, hi);
-    };
 
-    // exact face integrals
-    auto rface = [&](int i, V3& N, V3& T1, V3& T2) {   // r-face i - 1/2 of column (j, k)
-        const double R2 = t.R2[i], dp = dphi;
-        N = V3{R2 * (t.is2[j] * t.jc[k]), R2 * (t.is2[j] * t.js[k]), R2 * (t.isc[j] * dp)};
-        T1 = V3{R2 * (t.isc[j] * t.jc[k]), R2 * (t.isc[j] * t.js[k]), R2 * (-(t.is2[j] * dp))};
-        T2 = V3{R2 * (t.is[j] * -t.js[k]), R2 * (t.is[j] * t.jc[k]), 0.0};
-    };
-    auto tface = [&](int i, int jf, V3& N, V3& T1, V3& T2) {   // theta-face jf - 1/2 of row i, column k
-        const double rg = t.ring[i], st = t.fst[jf], ct = t.fct[jf];
-        N = V3{rg * ((st * ct) * t.jc[k]), rg * ((st * ct) * t.js[k]), rg * (-((st * st) * dphi))};
-        T1 = V3{rg * ((st * st) * t.jc[k]), rg * ((st * st) * t.js[k]), rg * ((st * ct) * dphi)};
-        T2 = V3{rg * (st * -t.js[k]), rg * (st * t.jc[k]), 0.0};
-    };
-    auto pface = [&](int i, int kf, V3& N, V3& T1, V3& T2) {   // phi-face kf + 1/2 of row i, column j
-        const double rg = t.ring[i], c1 = t.cp1[kf], s1 = t.sp1[kf];
-        N = V3{rg * (t.dth[j] * -s1), rg * (t.dth[j] * c1), 0.0};
-        T1 = V3{rg * (t.is[j] * c1), rg * (t.is[j] * s1), rg * t.ic[j]};
-        T2 = V3{rg * (t.ic[j] * c1), rg * (t.ic[j] * s1), rg * (-t.is[j])};
-    };
-
-    Patch pb, ph, pa;   // rows i - 1, i, i + 1
-    load(i0 - 1, pb);
-    load(i0, ph);
-    load(i0 + 1, pa);
-    // the lower r-face of the first row (face i0 - 1/2): its tangential parts
-    // are the means of cells i0 - 1 and i0 (cell i0's alone at the inner face)
-    V3 lowr;
-    {
-        V3 N, T1, T2;
-        rface(i0, N, T1, T2);
-        const double gn = (ph.v[1][1] - pb.v[1][1]) * t.invdr[i0];
-        double g1, g2;
-        if (i0 == 0) {
-            g1 = ct_of(ph, i0, 1, 1);
-            g2 = cp_of(ph, i0, 1, 1);
-        } else {
-            g1 = avg(ct_of(pb, i0 - 1, 1, 1), ct_of(ph, i0, 1, 1));
-            g2 = avg(cp_of(pb, i0 - 1, 1, 1), cp_of(ph, i0, 1, 1));
+    // the components of row i from its 3 x 3 patch P, the radial quotients of
+    // its lower face (grl) and of its upper face (grh) at the five columns
+    auto comps = [&](int i, const double (&P)[3][3], const double (&grl)[5], const double (&grh)[5], RowComps& C) {
+        const double ir = t.invr[i];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            C.grh[c] = grh[c];
+            C.cr[c] = avg(grl[c], grh[c]);
         }
-        lowr = stress(gn, g1, g2, N, T1, T2, k4);
-    }
-    for (int i = i0; i < i1; ++i) {
-        Patch pn;
-        load(i + 2, pn);   // the next row ahead (clamped)
-        V3 N, T1, T2;
-        // upper r-face i + 1/2 (face index i + 1)
-        V3 upr;
-        {
-            rface(i + 1, N, T1, T2);
-            double gn, g1, g2;
-            if (i + 1 < nr) {
-                gn = (pa.v[1][1] - ph.v[1][1]) * t.invdr[i + 1];
-                g1 = avg(ct_of(ph, i, 1, 1), ct_of(pa, i + 1, 1, 1));
-                g2 = avg(cp_of(ph, i, 1, 1), cp_of(pa, i + 1, 1, 1));
-            } else {
-                gn = go[1][1];
-                g1 = ct_of(ph, i, 1, 1);
-                g2 = cp_of(ph, i, 1, 1);
+        const double rtl = ir * qtl, rth = ir * qth;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double lo = (P[1][b] - P[0][b]) * rtl, hi = (P[2][b] - P[1][b]) * rth;
+            C.ct[b] = avg(lo, hi);
+            if (b == 1) {
+                C.gtl = lo;
+                C.gth = hi;
             }
-            upr = stress(gn, g1, g2, N, T1, T2, k4);
         }
-        // theta-faces j - 1/2 (face index j) and j + 1/2 (face index j + 1):
-        // normal quotient, radial and phi parts as means of the two cells
-        V3 lowt, upt;
-        {
-            tface(i, j, N, T1, T2);
-            const double gn = (ph.v[1][1] - ph.v[0][1]) * t.invr[i] * t.invdthc[j];
-            const double g1 = avg(cr_of(pb, ph, pa, i, 0, 1), cr_of(pb, ph, pa, i, 1, 1));
-            const double g2 = avg(cp_of(ph, i, 0, 1), cp_of(ph, i, 1, 1));
-            lowt = stress(gn, g1, g2, N, T1, T2, k4);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double rp = ir * qp[a];
+            const double lo = (P[a][1] - P[a][0]) * rp, hi = (P[a][2] - P[a][1]) * rp;
+            C.cp[a] = avg(lo, hi);
+            if (a == 1) {
+                C.gpl = lo;
+                C.gph = hi;
+            }
         }
-        {
-            tface(i, j + 1, N, T1, T2);
-            const double gn = (ph.v[2][1] - ph.v[1][1]) * t.invr[i] * t.invdthc[j + 1];
-            const double g1 = avg(cr_of(pb, ph, pa, i, 1, 1), cr_of(pb, ph, pa, i, 2, 1));
-            const double g2 = avg(cp_of(ph, i, 1, 1), cp_of(ph, i, 2, 1));
-            upt = stress(gn, g1, g2, N, T1, T2, k4);
+    };
+    // row i of the field (clamped into range: rows outside are never used)
+    auto load_patch = [&](int i, double (&P)[3][3]) {
+        const char* __restrict__ row =
+            reinterpret_cast<const char*>(phi + size_t(i < 0 ? 0 : (i < nr ? i : nr - 1)) * plane);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) P[a][b] = *reinterpret_cast<const double*>(row + off[a][b]);
+    };
+    // radial quotients of face i + 1/2 (rows i and i + 1 at the five columns;
+    // the outer face's extrapolated derivative for i = N_r - 1)
+    auto rquot = [&](int i, const double (&P)[3][3], const double (&Q)[3][3], double (&g)[5]) {
+        if (i + 1 < nr) {
+            const double f = t.invdr[i + 1];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) g[c] = (Q[PA[c]][PB[c]] - P[PA[c]][PB[c]]) * f;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                g[c] = -*reinterpret_cast<const double*>(reinterpret_cast<const char*>(tout) + off[PA[c]][PB[c]]) * inv_ro2;
         }
-        // phi-faces k - 1/2 (that of column k - 1) and k + 1/2
-        V3 lowp, upp;
-        {
-            pface(i, km, N, T1, T2);
-            const double gn = (ph.v[1][1] - ph.v[1][0]) * t.invr[i] * t.invsdp[j];
-            const double g1 = avg(cr_of(pb, ph, pa, i, 1, 0), cr_of(pb, ph, pa, i, 1, 1));
-            const double g2 = avg(ct_of(ph, i, 1, 0), ct_of(ph, i, 1, 1));
-            lowp = stress(gn, g1, g2, N, T1, T2, k4);
+    };
+
+    // prologue: rows i0 - 1, i0 and i0 + 1, and row i0 + 2 in flight (each
+    // row's patch is loaded one iteration before its first use)
+    double Pb[3][3], P[3][3], Pn[3][3], Pf[3][3], grl[5], grh[5];
+    RowComps C;
+    V3 lowr;
+    load_patch(i0 - 1, Pb);
+    load_patch(i0, P);
+    load_patch(i0 + 1, Pn);
+    load_patch(i0 + 2, Pf);
+    {
+        const double f = t.invdr[i0];   // 0 at the inner face
+#pragma unroll
+        for (int c = 0; c < 5; ++c) grl[c] = (P[PA[c]][PB[c]] - Pb[PA[c]][PB[c]]) * f;
+        rquot(i0, P, Pn, grh);
+        comps(i0, P, grl, grh, C);
+        // the chunk's lower r-face i0 - 1/2: tangential parts the means of
+        // cells i0 - 1 and i0 (cell i0's alone at the inner face)
+        double g1 = C.ct[1], g2 = C.cp[1];
+        if (i0 > 0) {
+            RowComps Cb;
+            comps(i0 - 1, Pb, grl, grl, Cb);   // its theta and phi parts only are used
+            g1 = avg(Cb.ct[1], C.ct[1]);
+            g2 = avg(Cb.cp[1], C.cp[1]);
         }
-        {
-            pface(i, k, N, T1, T2);
-            const double gn = (ph.v[1][2] - ph.v[1][1]) * t.invr[i] * t.invsdp[j];
-            const double g1 = avg(cr_of(pb, ph, pa, i, 1, 1), cr_of(pb, ph, pa, i, 1, 2));
-            const double g2 = avg(ct_of(ph, i, 1, 1), ct_of(ph, i, 1, 2));
-            upp = stress(gn, g1, g2, N, T1, T2, k4);
+        const double s = k4 * t.R2[i0];
+        lowr = rvec(scalars(grl[0], g1, g2, s, 0.5 * s), S2, SC, SN, jck, jsk, dphi);
+    }
+
+    for (int i = i0; i < i1; ++i) {
+        // theta- and phi-faces of row i
+        const double sr = k4 * t.ring[i], hsr = 0.5 * sr;
+        const V3 lowt = tvec(scalars(C.gtl, avg(C.cr[1], C.cr[0]), avg(C.cp[0], C.cp[1]), sr, hsr), sctl, ssl, stl,
+                             jck, jsk, dphi);
+        const V3 upt = tvec(scalars(C.gth, avg(C.cr[0], C.cr[2]), avg(C.cp[1], C.cp[2]), sr, hsr), scth, ssh, sth,
+                            jck, jsk, dphi);
+        const V3 lowp = pvec(scalars(C.gpl, avg(C.cr[3], C.cr[0]), avg(C.ct[0], C.ct[1]), sr, hsr), D, SN, CS, c1l, s1l);
+        const V3 upp = pvec(scalars(C.gph, avg(C.cr[0], C.cr[4]), avg(C.ct[1], C.ct[2]), sr, hsr), D, SN, CS, c1h, s1h);
+        const V3 side{(upt.x - lowt.x) + (upp.x - lowp.x), (upt.y - lowt.y) + (upp.y - lowp.y),
+                      (upt.z - lowt.z) + (upp.z - lowp.z)};
+        // upper r-face i + 1/2: the next row's components first (the outer
+        // face of the last row takes its one cell's tangential parts)
+        double g1 = C.ct[1], g2 = C.cp[1];
+        const double gn = C.grh[0];
+        if (i + 1 < nr) {
+            double Pnn[3][3], gnx[5];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Pnn[a][b] = Pf[a][b];
+            load_patch(i + 3, Pf);
+            rquot(i + 1, Pn, Pnn, gnx);
+            RowComps Cn;
+            comps(i + 1, Pn, C.grh, gnx, Cn);
+            g1 = avg(C.ct[1], Cn.ct[1]);
+            g2 = avg(C.cp[1], Cn.cp[1]);
+            C = Cn;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Pn[a][b] = Pnn[a][b];
         }
-        const size_t at = size_t(i) * plane + e;
-        __builtin_nontemporal_store(-(((upr.x - lowr.x) + (upt.x - lowt.x)) + (upp.x - lowp.x)), fx + at);
-        __builtin_nontemporal_store(-(((upr.y - lowr.y) + (upt.y - lowt.y)) + (upp.y - lowp.y)), fy + at);
-        __builtin_nontemporal_store(-(((upr.z - lowr.z) + (upt.z - lowt.z)) + (upp.z - lowp.z)), fz + at);
+        const double s = k4 * t.R2[i + 1];
+        const V3 upr = rvec(scalars(gn, g1, g2, s, 0.5 * s), S2, SC, SN, jck, jsk, dphi);
+        const size_t o = size_t(i) * plane + e;
+        __builtin_nontemporal_store(-((upr.x - lowr.x) + side.x), fx + o);
+        __builtin_nontemporal_store(-((upr.y - lowr.y) + side.y), fy + o);
+        __builtin_nontemporal_store(-((upr.z - lowr.z) + side.z), fz + o);
         lowr = upr;
-        pb = ph;
-        ph = pa;
-        pa = pn;
     }
 }
 

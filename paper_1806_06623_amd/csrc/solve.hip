@@ -849,7 +849,8 @@ __global__ __launch_bounds__(256) void k_refine_gate(spp_status_record* __restri
 // T_in (the regular inner condition; 0 for zero flux) on the inner face, T
 // per (j, k) from the shell transforms.  A thread owns one (j, k) column and
 // RROWS radial rows, with every load issued before the first store; the
-// neighbour rows come from cache (adjacent threads load them).
+// neighbour rows come from cache (adjacent threads load them; plane blocks in
+// the XCD-aware order of spp_plane_block).
 constexpr int RROWS = 4;
 
 __global__ __launch_bounds__(256) void k_residual_phys(const double* __restrict__ rho, const double* __restrict__ phi,
@@ -860,7 +861,7 @@ __global__ __launch_bounds__(256) void k_residual_phys(const double* __restrict_
 {
     const int plane = nth * nphi;
     const int chunk = blockIdx.x / gx;
-    const int e = (blockIdx.x - chunk * gx) * 256 + threadIdx.x;
+    const int e = spp_plane_block(blockIdx.x - chunk * gx, gx) * 256 + threadIdx.x;
     if (e >= plane) return;
     const int j = e / nphi, k = e - j * nphi;
     const int ekp = k + 1 < nphi ? e + 1 : e + 1 - nphi;
