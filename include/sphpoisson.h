@@ -38,7 +38,17 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* The enumerations below are passed as C ints.  Under C++ they get int as
+ * their fixed underlying type, so that an out-of-range value a caller passes
+ * is a valid value of the type (rejected with SPP_EINVAL) rather than
+ * undefined behaviour. */
+#ifdef __cplusplus
+#define SPP_ENUM(tag) enum tag : int
+#else
+#define SPP_ENUM(tag) enum tag
+#endif
+
+typedef SPP_ENUM(spp_status_e) {
     SPP_OK = 0,
     SPP_EINVAL = -1,     /* invalid argument (sizes, interfaces, NULL pointers) */
     SPP_ENOTSUP = -2,    /* valid for the method, not supported by this build   */
@@ -51,7 +61,7 @@ typedef enum {
 
 /* Inner radial face r_{1/2} (the paper does not fix it; it matters only when
  * r_{1/2} > 0, since a face at r = 0 has no area). */
-typedef enum {
+typedef SPP_ENUM(spp_inner_bc_e) {
     SPP_INNER_AUTO = 0,      /* zero area when r_{1/2} = 0, else zero flux             */
     SPP_INNER_ZERO_FLUX = 1, /* no flux through the inner face (exact for l = 0 when
                                 no mass lies inside r_{1/2})                         */
@@ -62,7 +72,7 @@ typedef enum {
                                 the outer condition of Sec. 3.2)                     */
 } spp_inner_bc;
 
-typedef enum {
+typedef SPP_ENUM(spp_precision_e) {
     SPP_FP64 = 0,          /* all stages in float64                                */
     SPP_MIXED_FP32 = 1,    /* theta projections as FP32 MFMA products accumulated in
                               FP32; FFTs, radial solves, residual and the
@@ -70,7 +80,7 @@ typedef enum {
     SPP_MIXED_BF16X3 = 2   /* split-BF16 projections: reserved, SPP_ENOTSUP        */
 } spp_precision;
 
-typedef enum {
+typedef SPP_ENUM(spp_path_e) {
     SPP_PATH_AUTO = 0,     /* fused when the grid allows it, else staged           */
     SPP_PATH_STAGED = 1,   /* five kernels: FFT, projection, radial, projection, FFT */
     SPP_PATH_FUSED = 2     /* folded FFT, one per-mode kernel, folded inverse FFT  */

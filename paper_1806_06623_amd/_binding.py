@@ -9,7 +9,9 @@ import numpy as np
 # (streams, memory) of one are unknown to the other.
 import torch  # noqa: F401
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsphpoisson.so")
+# SPP_LIB names another build of the same library (the host-sanitized one of
+# the host-side tests); by default the library next to this file
+LIB_PATH = os.environ.get("SPP_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsphpoisson.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
