@@ -125,7 +125,13 @@ struct RowComps {
     double grh[5];
 };
 
-__global__ __launch_bounds__(THREADS) void k_momentum(const double* __restrict__ phi, const double* __restrict__ tout,
+// ROW_WAVES: every wave lies within one theta row (N_phi a multiple of 64),
+// so j and everything that depends on it are wave-uniform and live in
+// scalar registers.
+// At most 168 VGPRs (three waves per SIMD, a few values spilled): the
+// arithmetic chains of a row need the latency hiding more than the registers.
+template <bool ROW_WAVES>
+__global__ __launch_bounds__(THREADS, 3) void k_momentum(const double* __restrict__ phi, const double* __restrict__ tout,
                                                       double* __restrict__ fx, double* __restrict__ fy,
                                                       double* __restrict__ fz, Tables t, int nr, int nth, int nphi,
                                                       double dphi, double k4, double inv_ro2, int gx)
@@ -134,7 +140,8 @@ __global__ __launch_bounds__(THREADS) void k_momentum(const double* __restrict__
     const int chunk = blockIdx.x / gx;
     const int e = spp_plane_block(blockIdx.x - chunk * gx, gx) * THREADS + threadIdx.x;
     if (e >= plane) return;
-    const int j = e / nphi, k = e - j * nphi;
+    const int jl = e / nphi, k = e - jl * nphi;
+    const int j = ROW_WAVES ? __builtin_amdgcn_readfirstlane(jl) : jl;
     const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < nth ? j + 1 : nth - 1;
     const int km = k > 0 ? k - 1 : nphi - 1, kp = k + 1 < nphi ? k + 1 : 0;
     // 32-bit byte offsets of the 3 x 3 patch within a row of the field (a row
@@ -217,15 +224,15 @@ __global__ __launch_bounds__(THREADS) void k_momentum(const double* __restrict__
         }
     };
 
-    // prologue: rows i0 - 1, i0 and i0 + 1, and row i0 + 2 in flight (each
-    // row's patch is loaded one iteration before its first use)
-    double Pb[3][3], P[3][3], Pn[3][3], Pf[3][3], grl[5], grh[5];
+    // prologue: rows i0 - 1, i0 and i0 + 1 (each later row's patch is loaded in
+    // the iteration that first uses it: a patch kept in flight across
+    // iterations would cost the third wave per SIMD)
+    double Pb[3][3], P[3][3], Pn[3][3], grl[5], grh[5];
     RowComps C;
     V3 lowr;
     load_patch(i0 - 1, Pb);
     load_patch(i0, P);
     load_patch(i0 + 1, Pn);
-    load_patch(i0 + 2, Pf);
     {
         const double f = t.invdr[i0];   // 0 at the inner face
 #pragma unroll
@@ -262,11 +269,7 @@ __global__ __launch_bounds__(THREADS) void k_momentum(const double* __restrict__
         const double gn = C.grh[0];
         if (i + 1 < nr) {
             double Pnn[3][3], gnx[5];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Pnn[a][b] = Pf[a][b];
-            load_patch(i + 3, Pf);
+            load_patch(i + 2, Pnn);
             rquot(i + 1, Pn, Pnn, gnx);
             RowComps Cn;
             comps(i + 1, Pn, C.grh, gnx, Cn);

@@ -1201,8 +1201,11 @@ spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G,
     const int gx = (plane + momentum::THREADS - 1) / momentum::THREADS;
     const int chunks = (nr + momentum::MROWS - 1) / momentum::MROWS;
     const double ro = p->r_if[nr];
-    hipLaunchKernelGGL(momentum::k_momentum, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, B, fx, fy, fz, t, nr,
-                       nth, nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
+    // with N_phi a multiple of 64 every wave (64 consecutive plane elements
+    // from a multiple of 64) lies within one theta row
+    auto kern = nphi % 64 == 0 ? momentum::k_momentum<true> : momentum::k_momentum<false>;
+    hipLaunchKernelGGL(kern, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, B, fx, fy, fz, t, nr, nth, nphi,
+                       2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_momentum_source: ") + hipGetErrorString(e));
     return SPP_OK;
