@@ -230,7 +230,8 @@ def test_binding_rejects_fields_on_the_wrong_device():
     p.nr, p.nth, p.nphi = 3, 4, 8
     p.device = torch.device("cuda", 0)
     rho = torch.zeros((3, 4, 8), dtype=torch.float64)
-    for call in (lambda: p.solve(rho), lambda: p.solve_mixed(rho), lambda: p.face_fluxes(rho)):
+    for call in (lambda: p.solve(rho), lambda: p.solve_mixed(rho), lambda: p.face_fluxes(rho),
+                 lambda: p.momentum_source(rho), lambda: p.residual(rho, rho)):
         with pytest.raises(ValueError):
             call()
 

@@ -79,6 +79,8 @@ def _gpu_forces(plan, phi, G):
     (130, 128, 64, 0.0, "uniform", "blob"),
     (130, 128, 64, 0.0, "uniform", "random"),
     (5, 2, 4, 0.0, "uniform", "random"),
+    (20, 24, 128, 0.0, "uniform", "random"),     # two theta rows per workgroup
+    (12, 10, 512, 1.5, "skewed", "random"),      # a theta row across two workgroups
 ])
 def test_momentum_matches_oracle(nr, nth, nphi, r0, theta, field):
     import paper_1806_06623_amd as spp
