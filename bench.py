@@ -342,9 +342,10 @@ def main():
     torch.cuda.synchronize()
     # The first solves after process start find the GPU's clocks still ramping
     # up (the compute-bound per-mode kernel runs about 10% slower there); they
-    # are timed here as they come, for the record.  The headline below is the
+    # are timed here as they come, for the record.  Everything after them is the
     # steady state a simulation sees when it calls the solver every time step:
-    # it follows the other legs and a settling period of back-to-back solves.
+    # a settling period of back-to-back solves precedes the other legs and
+    # again the headline.
     for _ in range(args.warmup):
         plan.solve(rho, G=case["G"], out=phi)
     torch.cuda.synchronize()
@@ -357,6 +358,20 @@ def main():
             "note": f"the first {args.warmup} + {K} solves after process start (warm-up, then timed), before "
                     f"the GPU's clocks have ramped up"}
     log(f"cold start: {el_cold * 1e3 / K:.3f} ms/solve")
+
+    def settle_clocks():
+        """Back-to-back solves for args.settle_s seconds, so that the legs timed
+        next run at the clocks of a busy GPU."""
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < args.settle_s:
+            for _ in range(50):
+                plan.solve(rho, G=case["G"], out=phi)
+            n += 50
+            torch.cuda.synchronize()
+        return {"seconds": round(time.perf_counter() - t0, 3), "solves": n}
+
+    settle_clocks()
 
     # mixed-precision form on the same workload (FP32-MFMA projections + FP64 refinement)
     mixed = None
@@ -451,15 +466,7 @@ def main():
     serving = None if args.no_serving else serving_leg(spp, torch, synthetic, args.serving_requests,
                                                         (0.5, 0.8, 0.95))
 
-    # settling period: back-to-back solves until the clocks hold steady
-    t0 = time.perf_counter()
-    n_settle = 0
-    while time.perf_counter() - t0 < args.settle_s:
-        for _ in range(50):
-            plan.solve(rho, G=case["G"], out=phi)
-        n_settle += 50
-        torch.cuda.synchronize()
-    settle = {"seconds": round(time.perf_counter() - t0, 3), "solves": n_settle}
+    settle = settle_clocks()
     for _ in range(args.warmup):
         plan.solve(rho, G=case["G"], out=phi)
     torch.cuda.synchronize()
