@@ -8,6 +8,14 @@ solve: forward real FFT along phi, forward theta projection, radial
 tridiagonal solves with the outer boundary condition, inverse projection,
 inverse FFT.  Inputs are resident in HBM before the timed region.
 
+Order of a run: set-up; the first solves after process start, timed as they
+come (``cold_start``: the GPU's clocks are still ramping); a settling period
+of back-to-back solves; the other legs (mixed form, face fluxes, momentum
+source, a device copy of one field as the practical HBM rate, batched and
+served solves); another settling period (``settle``), the W warm-up solves
+and the K timed ones (``value``), the latency loop and the per-stage profile;
+finally the FP64 oracle timed on the host CPU.
+
 Prints one JSON line (rank 0, N = 1) with solves/s as ``value``, Gzones/s,
 per-solve latency percentiles, per-stage times and roofline fractions, the
 error against the FP64 oracle, and the oracle itself timed on the host CPU.
