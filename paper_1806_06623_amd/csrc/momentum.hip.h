@@ -36,7 +36,8 @@
 namespace momentum {
 
 constexpr int THREADS = 256;
-constexpr int MROWS = 8;
+constexpr int MROWS = 8;        // radial rows per thread (k_momentum)
+constexpr int ROWS_LDS = 8;     // radial rows per thread (k_momentum_rows)
 
 // Per-index factors of the face integrals and difference quotients (device
 // tables of the plan).  Index conventions: r-faces i = 0..N_r (face i - 1/2),
@@ -288,6 +289,179 @@ __global__ __launch_bounds__(THREADS, 3) void k_momentum(const double* __restric
         __builtin_nontemporal_store(-((upr.y - lowr.y) + side.y), fy + o);
         __builtin_nontemporal_store(-((upr.z - lowr.z) + side.z), fz + o);
         lowr = upr;
+    }
+}
+
+// Workgroups that hold whole theta rows (64 <= N_phi <= THREADS, N_phi
+// dividing THREADS): every cell's phi neighbours are in its workgroup.  The
+// cells of a row then exchange through LDS what both sides of a phi-face need,
+// instead of each recomputing its neighbours': Phi of its column at theta rows
+// j-1, j, j+1 (the neighbours' phi quotients), its radial and theta centred
+// components, and its upper phi-face's stress vector, which the next cell
+// takes as its lower one (each phi-face evaluated once).  Theta-faces are
+// still evaluated by both cells, by the same code from the same values; the
+// r-face between two rows once.  Two barriers per row: after the centred
+// components (the row's Phi having been exchanged in the previous row's
+// step), and after the phi-faces.  Phi is double-buffered in LDS by row.
+// Threads past the end of the plane (a last workgroup with whole rows past
+// N_theta) take part in the barriers and store nothing.
+__global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restrict__ phi,
+                                                           const double* __restrict__ tout, double* __restrict__ fx,
+                                                           double* __restrict__ fy, double* __restrict__ fz, Tables t,
+                                                           int nr, int nth, int nphi, double dphi, double k4,
+                                                           double inv_ro2, int gx)
+{
+    __shared__ double sphi[2][3][THREADS];   // Phi of row i (buffer i % 2) at theta rows j-1, j, j+1, per cell
+    __shared__ double scomp[2][THREADS];     // radial and theta centred components of the current row, per cell
+    __shared__ double sface[3][THREADS];     // the upper phi-face's stress vector, per cell
+    const int plane = nth * nphi;
+    const int chunk = blockIdx.x / gx;
+    const int tid = threadIdx.x;
+    const int e = spp_plane_block(blockIdx.x - chunk * gx, gx) * THREADS + tid;
+    const bool valid = e < plane;
+    const int jl = e / nphi, k = e - jl * nphi;
+    const int jw = __builtin_amdgcn_readfirstlane(jl);   // every wave lies within one theta row
+    const int j = jw < nth ? jw : nth - 1;
+    const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < nth ? j + 1 : nth - 1;
+    const int ln = k > 0 ? tid - 1 : tid + nphi - 1;      // LDS slot of the cell k - 1 (periodic)
+    const int rn = k + 1 < nphi ? tid + 1 : tid - nphi + 1;
+    const int ec = valid ? k : 0;
+    const int col[3] = {jm * nphi + ec, j * nphi + ec, jp * nphi + ec};
+    const int i0 = chunk * ROWS_LDS;
+    const int i1 = i0 + ROWS_LDS < nr ? i0 + ROWS_LDS : nr;
+
+    const double jck = t.jc[ec], jsk = t.js[ec], c1 = t.cp1[ec], s1 = t.sp1[ec];
+    const double S2 = t.is2[j], SC = t.isc[j], SN = t.is[j], CS = t.ic[j], D = t.dth[j];
+    const double stl = t.fst[j], sth = t.fst[j + 1];
+    const double sctl = stl * t.fct[j], ssl = stl * stl, scth = sth * t.fct[j + 1], ssh = sth * sth;
+    const double qtl = t.invdthc[j], qth = t.invdthc[j + 1];
+    const double qp[3] = {t.invsdp[jm], t.invsdp[j], t.invsdp[jp]};
+
+    auto column = [&](int i, double (&v)[3]) {
+        const double* __restrict__ row = phi + size_t(i < 0 ? 0 : (i < nr ? i : nr - 1)) * plane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = row[col[a]];
+    };
+    auto publish = [&](int i, const double (&v)[3]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sphi[i & 1][a][tid] = v[a];
+    };
+    // the own column's theta and phi centred components of row i from its
+    // column values v and the neighbours' published ones
+    auto own_tp = [&](int i, const double (&v)[3], double& ct, double& cp, double& gtl, double& gth, double& gpl,
+                      double& gph) {
+        const double ir = t.invr[i];
+        gtl = (v[1] - v[0]) * (ir * qtl);
+        gth = (v[2] - v[1]) * (ir * qth);
+        ct = avg(gtl, gth);
+        const double rp = ir * qp[1];
+        gpl = (v[1] - sphi[i & 1][1][ln]) * rp;
+        gph = (sphi[i & 1][1][rn] - v[1]) * rp;
+        cp = avg(gpl, gph);
+    };
+    // radial quotients of face i + 1/2 at the three columns (the outer face:
+    // the extrapolated derivative)
+    auto rquot = [&](int i, const double (&v)[3], const double (&w)[3], double (&g)[3]) {
+        if (i + 1 < nr) {
+            const double f = t.invdr[i + 1];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[a] = (w[a] - v[a]) * f;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[a] = -tout[col[a]] * inv_ro2;
+        }
+    };
+
+    // prologue: rows i0 - 1, i0 (published) and i0 + 1; the chunk's lower
+    // r-face i0 - 1/2 (tangential parts the means of cells i0 - 1 and i0,
+    // cell i0's alone at the inner face)
+    double prev[3], cur[3], nxt[3], grl[3];
+    column(i0 - 1, prev);
+    column(i0, cur);
+    column(i0 + 1, nxt);
+    publish(i0 - 1, prev);
+    publish(i0, cur);
+    __syncthreads();
+    V3 lowr;
+    {
+        const double f = t.invdr[i0];   // 0 at the inner face
+#pragma unroll
+        for (int a = 0; a < 3; ++a) grl[a] = (cur[a] - prev[a]) * f;
+        double ct0, cp0, x0, x1, x2, x3;
+        own_tp(i0, cur, ct0, cp0, x0, x1, x2, x3);
+        double g1 = ct0, g2 = cp0;
+        if (i0 > 0) {
+            double ctb, cpb;
+            own_tp(i0 - 1, prev, ctb, cpb, x0, x1, x2, x3);
+            g1 = avg(ctb, ct0);
+            g2 = avg(cpb, cp0);
+        }
+        const double sr = k4 * t.R2[i0];
+        lowr = rvec(scalars(grl[1], g1, g2, sr, 0.5 * sr), S2, SC, SN, jck, jsk, dphi);
+    }
+    __syncthreads();   // the buffer of row i0 - 1 is rewritten with row i0 + 1 below
+
+    for (int i = i0; i < i1; ++i) {
+        double nn[3];
+        column(i + 2, nn);    // in flight through this row
+        publish(i + 1, nxt);
+        // row i: radial components at the three columns, theta and phi ones
+        // of the own column, phi ones of the columns j -+ 1
+        double grh[3], cr[3], cp[3];
+        rquot(i, cur, nxt, grh);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cr[a] = avg(grl[a], grh[a]);
+        double ct, gtl, gth, gpl, gph;
+        own_tp(i, cur, ct, cp[1], gtl, gth, gpl, gph);
+        const double ir = t.invr[i];
+#pragma unroll
+        for (int a = 0; a < 3; a += 2) {
+            const double rp = ir * qp[a];
+            cp[a] = avg((cur[a] - sphi[i & 1][a][ln]) * rp, (sphi[i & 1][a][rn] - cur[a]) * rp);
+        }
+        scomp[0][tid] = cr[1];
+        scomp[1][tid] = ct;
+        __syncthreads();
+
+        const double sr = k4 * t.ring[i], hsr = 0.5 * sr;
+        // upper phi-face k + 1/2, evaluated here once
+        const V3 upp = pvec(scalars(gph, avg(cr[1], scomp[0][rn]), avg(ct, scomp[1][rn]), sr, hsr), D, SN, CS, c1, s1);
+        sface[0][tid] = upp.x;
+        sface[1][tid] = upp.y;
+        sface[2][tid] = upp.z;
+        // theta-faces j - 1/2 and j + 1/2
+        const V3 lowt = tvec(scalars(gtl, avg(cr[0], cr[1]), avg(cp[0], cp[1]), sr, hsr), sctl, ssl, stl, jck, jsk,
+                             dphi);
+        const V3 upt = tvec(scalars(gth, avg(cr[1], cr[2]), avg(cp[1], cp[2]), sr, hsr), scth, ssh, sth, jck, jsk,
+                            dphi);
+        // upper r-face i + 1/2: the next row's own theta and phi components
+        // (its Phi published above), or the cell's own at the outer face
+        double g1 = ct, g2 = cp[1];
+        if (i + 1 < nr) {
+            double ctn, cpn, x0, x1, x2, x3;
+            own_tp(i + 1, nxt, ctn, cpn, x0, x1, x2, x3);
+            g1 = avg(ct, ctn);
+            g2 = avg(cp[1], cpn);
+        }
+        const double srr = k4 * t.R2[i + 1];
+        const V3 upr = rvec(scalars(grh[1], g1, g2, srr, 0.5 * srr), S2, SC, SN, jck, jsk, dphi);
+        __syncthreads();
+
+        // lower phi-face k - 1/2: the cell k - 1's upper one
+        const V3 lowp{sface[0][ln], sface[1][ln], sface[2][ln]};
+        if (valid) {
+            const size_t o = size_t(i) * plane + e;
+            __builtin_nontemporal_store(-(((upr.x - lowr.x) + (upt.x - lowt.x)) + (upp.x - lowp.x)), fx + o);
+            __builtin_nontemporal_store(-(((upr.y - lowr.y) + (upt.y - lowt.y)) + (upp.y - lowp.y)), fy + o);
+            __builtin_nontemporal_store(-(((upr.z - lowr.z) + (upt.z - lowt.z)) + (upp.z - lowp.z)), fz + o);
+        }
+        lowr = upr;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            grl[a] = grh[a];
+            cur[a] = nxt[a];
+            nxt[a] = nn[a];
+        }
     }
 }
 

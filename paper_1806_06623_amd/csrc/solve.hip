@@ -1201,11 +1201,19 @@ spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G,
     const int gx = (plane + momentum::THREADS - 1) / momentum::THREADS;
     const int chunks = (nr + momentum::MROWS - 1) / momentum::MROWS;
     const double ro = p->r_if[nr];
-    // with N_phi a multiple of 64 every wave (64 consecutive plane elements
-    // from a multiple of 64) lies within one theta row
-    auto kern = nphi % 64 == 0 ? momentum::k_momentum<true> : momentum::k_momentum<false>;
-    hipLaunchKernelGGL(kern, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, B, fx, fy, fz, t, nr, nth, nphi,
-                       2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
+    // workgroups of whole theta rows (64 <= N_phi <= 256) share the phi-faces
+    // through LDS; otherwise with N_phi a multiple of 64 every wave (64
+    // consecutive plane elements from a multiple of 64) still lies within one
+    // theta row
+    if (nphi >= 64 && momentum::THREADS % nphi == 0) {
+        const int lchunks = (nr + momentum::ROWS_LDS - 1) / momentum::ROWS_LDS;
+        hipLaunchKernelGGL(momentum::k_momentum_rows, dim3(gx * lchunks), dim3(momentum::THREADS), 0, s, phi, B, fx,
+                           fy, fz, t, nr, nth, nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
+    } else {
+        auto kern = nphi % 64 == 0 ? momentum::k_momentum<true> : momentum::k_momentum<false>;
+        hipLaunchKernelGGL(kern, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, B, fx, fy, fz, t, nr, nth,
+                           nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_momentum_source: ") + hipGetErrorString(e));
     return SPP_OK;
