@@ -80,14 +80,14 @@ def stage_model(nr, nth, nphi, parity, fused):
 TRAFFIC = {
     "modal::k_modal": {"grid": (550, 128, 256),
                        "sources": ("modal.hip.h", "modal_layout.h", "radial.hip.h", "status.h", "solve.hip"),
-                       "source_digest": "9db9a298fa8fb9b9",
-                       "bytes_per_launch": (81368.6 * 2.0 + 140806.0) * 1024.0},
+                       "source_digest": "aaf4139023c36863",
+                       "bytes_per_launch": (81372.6 * 2.0 + 140806.0) * 1024.0},
     "faceflux::k_face_fluxes": {"grid": (550, 128, 256), "sources": ("fluxes.hip.h", "xcd.h", "solve.hip"),
-                                "source_digest": "fd22b1e1a2e1810f",
-                                "bytes_per_launch": (74482.5 * 2.0 + 422610.1) * 1024.0},
-    "momentum::k_momentum": {"grid": (550, 128, 256), "sources": ("momentum.hip.h", "xcd.h", "solve.hip"),
-                             "source_digest": "07f5bcb1b2a5ca21",
-                             "bytes_per_launch": (78999.5 * 2.0 + 492743.7) * 1024.0},
+                                "source_digest": "539d87d72cd94858",
+                                "bytes_per_launch": (74482.7 * 2.0 + 422573.6) * 1024.0},
+    "momentum::k_momentum_rows": {"grid": (550, 128, 256), "sources": ("momentum.hip.h", "xcd.h", "solve.hip"),
+                                  "source_digest": "5b3201f08039852d",
+                                  "bytes_per_launch": (78458.9 * 2.0 + 422400.4) * 1024.0},
 }
 
 
@@ -403,7 +403,7 @@ def main():
     face = None
     if not args.no_fluxes:
         fl = tuple(torch.empty_like(phi) for _ in range(3))
-        for _ in range(min(args.warmup, 20)):
+        for _ in range(20):
             plan.face_fluxes(phi, out=fl)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -427,7 +427,7 @@ def main():
     mom = None
     if not args.no_momentum:
         F = tuple(torch.empty_like(phi) for _ in range(3))
-        for _ in range(min(args.warmup, 20) + 1):
+        for _ in range(20):
             plan.momentum_source(phi, G=case["G"], out=F)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -442,7 +442,7 @@ def main():
                "hbm_frac": round(mbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "note": "whole entry point: outer-face gradient (shell FFT, per-mode beta, inverse FFT) and the "
                        "stress-tensor face sums; algorithmic bytes = Phi read once + three force fields",
-               "kernel_traffic": measured_traffic("momentum::k_momentum", nr, nth, nphi)}
+               "kernel_traffic": measured_traffic("momentum::k_momentum_rows", nr, nth, nphi)}
         log(f"momentum source: {ms * 1e3:.1f} us per call, {mom['GBps']} GB/s")
         del F
 
