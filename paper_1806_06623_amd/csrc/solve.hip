@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "fft.hip.h"
+#include "fftfold.hip.h"
 #include "fluxes.hip.h"
 #include "internal.h"
 #include "modal.hip.h"
@@ -662,6 +663,15 @@ void launch_fft_pair(bool forward, const double* in, double* out, const c64* tw,
     const int res = fft_resident<N>(forward, fold);
     const int per = (nblocks + res - 1) / res;
     const int grid = (nblocks + per - 1) / per;
+    if (fold && N == fftfold::N) {   // one block of 16 line pairs per workgroup
+        if (forward)
+            hipLaunchKernelGGL(fftfold::k_rfft_fwd_fold, dim3(nblocks * x.nrhs), dim3(fftfold::THREADS), 0, s, in, out,
+                               tw, scale, nlines, nblocks, nth, x.rec, x.gate, x.bv);
+        else
+            hipLaunchKernelGGL(fftfold::k_rfft_inv_fold, dim3(nblocks * x.nrhs), dim3(fftfold::THREADS), 0, s, in, out,
+                               tw, nlines, nblocks, nth, x.rec, x.gate, x.bv);
+        return;
+    }
     if (forward) {
         if (fold)   // one block per workgroup (see k_rfft_fwd)
             hipLaunchKernelGGL((k_rfft_fwd<N, true, false>), dim3(nblocks * x.nrhs), dim3(512), 0, s, in, out, tw,

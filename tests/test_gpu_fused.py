@@ -65,6 +65,8 @@ def _both_paths(r_if, th_if, nphi, rho):
     (385, 128, 8, 16),    # three tiles, h = 64
     (576, 128, 32, 17),   # largest N_r of the fused kernel
     (40, 16, 1024, 18),   # 2048 workgroups: the paired unit order far past one round
+    (7, 12, 256, 19),     # register-pass folded FFTs: 42 pairs, blocks span rows, ragged last block
+    (9, 100, 256, 20),    # 450 pairs, h = 50
 ])
 def test_fused_matches_oracle_and_staged(nr, nth, nphi, seed):
     print(f"[case] fused {nr}x{nth}x{nphi} seed {seed}", flush=True)
