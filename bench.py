@@ -446,28 +446,39 @@ def main():
         log(f"momentum source: {ms * 1e3:.1f} us per call, {mom['GBps']} GB/s")
         del F
 
-    # a device copy of one field (torch), from five distinct sources so that
-    # none is read from the last-level cache: the practical HBM rate for one
-    # read and one write stream, beside the 8 TB/s peak
-    copy = None
+    # copies of one field from five distinct sources (so that none is read
+    # from the last-level cache): torch's device copy (`hbm_copy`; its
+    # FETCH_SIZE/WRITE_SIZE counters calibrate the traffic figures) and the
+    # library's streaming copy (`hbm_stream`, spp_stream_copy): one read and
+    # one write stream, the rate the memory-bound kernels are set against
+    # beside the 8 TB/s peak
+    copy = stream = None
     if not args.no_copy:
         srcs = [torch.full_like(rho, float(i + 1)) for i in range(5)]
         dst = torch.empty_like(rho)
-        for a in srcs:
-            dst.copy_(a)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        n_copy = max(5, (K // 5) * 5)
-        torch.cuda.synchronize()
-        e0.record()
-        for k in range(n_copy):
-            dst.copy_(srcs[k % 5])
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / n_copy
         cbytes = 2 * 8.0 * zones
-        copy = {"ms": round(ms, 5), "bytes": cbytes, "GBps": round(cbytes / (ms * 1e-3) / 1e9, 1),
-                "hbm_frac": round(cbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        log(f"device copy of one field: {ms * 1e3:.1f} us, {copy['GBps']} GB/s")
+        n_copy = max(5, (K // 5) * 5)
+
+        def timed_copies(fn):
+            for a in srcs:
+                fn(a)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for k in range(n_copy):
+                fn(srcs[k % 5])
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / n_copy
+            return {"ms": round(ms, 5), "bytes": cbytes, "GBps": round(cbytes / (ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(cbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+        copy = timed_copies(lambda a: dst.copy_(a))
+        stream = timed_copies(lambda a: spp.stream_copy(a, dst))
+        if not torch.equal(dst, srcs[(n_copy - 1) % 5]):
+            raise RuntimeError("spp_stream_copy did not reproduce its source")
+        log(f"device copy of one field: {copy['ms'] * 1e3:.1f} us, {copy['GBps']} GB/s; "
+            f"streaming copy: {stream['ms'] * 1e3:.1f} us, {stream['GBps']} GB/s")
         del srcs, dst
 
     batch = None if args.no_batch else batched_leg(spp, torch, synthetic, args.batch_steps)
@@ -545,6 +556,11 @@ def main():
                                f"{k_ms * 1e3:.1f} us (HIP events on the solve stream); ideal {t_hbm * 1e6:.1f} us at "
                                f"the HBM peak, {t_mfma * 1e6:.1f} us at the FP64 matrix peak")}
 
+    # memory-bound figures against the streaming copy's rate as well
+    if stream is not None:
+        for d in [v for k, v in stages.items() if k != "fused_modal"] + [face, mom]:
+            if d is not None:
+                d["stream_frac"] = round(d["GBps"] / stream["GBps"], 4)
     if mixed is not None:
         mixed["speedup_vs_fp64"] = round(elapsed / (mixed["ms_per_step"] * 1e-3 * K), 3)
     phi_np = phi.cpu().numpy()
@@ -567,6 +583,7 @@ def main():
         "face_fluxes": face,
         "momentum_source": mom,
         "hbm_copy": copy,
+        "hbm_stream": stream,
         "batched": batch,
         "serving": serving,
     }

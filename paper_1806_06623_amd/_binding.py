@@ -124,6 +124,8 @@ lib.spp_plan_shape.argtypes = [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_in
 lib.spp_plan_shape.restype = _c_int
 lib.spp_last_error.argtypes = []
 lib.spp_last_error.restype = ctypes.c_char_p
+lib.spp_stream_copy.argtypes = [_vp, _vp, _c_size_t, _vp]
+lib.spp_stream_copy.restype = _c_int
 
 precision_codes = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16x3": 2}
 inner_codes = {"auto": 0, "zero_flux": 1, "regular": 2}
@@ -152,6 +154,20 @@ def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def stream_copy(src, dst, stream=None):
+    """Enqueue spp_stream_copy of the contiguous CUDA tensor src into dst (same
+    number of bytes, a multiple of 16) on ``stream`` (default: the current
+    torch stream): the streaming-rate reference of the memory-bound kernels
+    (include/spp_reference.h)."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("stream_copy: contiguous CUDA tensors required")
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: src and dst differ in size")
+    _check(lib.spp_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                               _stream_ptr(stream)), "spp_stream_copy")
 
 
 class Plan:

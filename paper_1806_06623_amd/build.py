@@ -25,7 +25,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB_SAN = os.path.join(HERE, "libsphpoisson_san.so")
 OBJDIR_SAN = os.path.join(HERE, "_build_san")
 
-SOURCES = ["plan.cpp", "eigen_ql.cpp", "solve.hip", "batch.cpp", "server.cpp", "noalloc.hip"]
+SOURCES = ["plan.cpp", "eigen_ql.cpp", "solve.hip", "batch.cpp", "server.cpp", "noalloc.hip", "stream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall", "-Wno-unused-result"]

@@ -280,3 +280,15 @@ def test_residual_status_and_hook_argument_checks():
     assert lib.spp_plan_scale_lowprec_basis(None, 2.0) == -1
     lib.spp_plan_destroy(p)
     lib.spp_grid_destroy(g)
+
+
+def test_stream_copy_argument_checks_on_the_host():
+    """spp_stream_copy (the streaming-rate reference): an empty copy enqueues
+    nothing, and NULL, misaligned or ragged arguments are rejected before any
+    device call."""
+    v = ctypes.c_void_p
+    assert lib.spp_stream_copy(None, None, 0, None) == 0
+    assert lib.spp_stream_copy(None, v(4096), 16, None) == -1
+    assert lib.spp_stream_copy(v(4096), v(8192), 24, None) == -1
+    assert lib.spp_stream_copy(v(4104), v(8192), 32, None) == -1
+    assert b"multiples of 16" in lib.spp_last_error()

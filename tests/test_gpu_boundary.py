@@ -171,3 +171,19 @@ def test_noalloc_status():
     bad[0, 0, 0] = float("nan")
     plan.solve_noalloc(bad)
     assert plan.status(noalloc=True)["status"] == "enonfinite"
+
+
+def test_stream_copy_is_exact():
+    """The streaming-copy reference moves every byte: one stellar field
+    (550 x 128 x 256, more elements than one sweep of its grid) and a ragged
+    size."""
+    import torch
+    import paper_1806_06623_amd as spp
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for n in (550 * 128 * 256, 2 * 1037):
+        print(f"[case] stream copy of {n} doubles", flush=True)
+        src = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        dst = torch.full_like(src, float("nan"))
+        spp.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
