@@ -31,6 +31,7 @@
 #include "fft.hip.h"
 #include "internal.h"
 #include "status.h"
+#include "xcd.h"
 
 namespace fftfold {
 
@@ -207,6 +208,10 @@ __global__ __launch_bounds__(THREADS, 4) void k_rfft_inv_fold(const double* __re
         X += r * bv.xstride;
         if (flag) flag += r;
     }
+    // blocks of one XCD cover a contiguous range of lines, so that the
+    // 128-byte runs of a component plane read by neighbouring blocks come
+    // through the same L2 at about the same time
+    blk = spp_plane_block(blk, nblocks);
     __shared__ c64 lds[2 * PB * LS];
     __shared__ c64 tws[N];
     if (threadIdx.x < N) tws[threadIdx.x] = tw_g[threadIdx.x];
