@@ -67,6 +67,7 @@ def _both_paths(r_if, th_if, nphi, rho):
     (40, 16, 1024, 18),   # 2048 workgroups: the paired unit order far past one round
     (7, 12, 256, 19),     # register-pass folded FFTs: 42 pairs, blocks span rows, ragged last block
     (9, 100, 256, 20),    # 450 pairs, h = 50
+    (64, 16, 256, 21),    # 32 blocks of 16 pairs: the XCD-ordered block range of the inverse
 ])
 def test_fused_matches_oracle_and_staged(nr, nth, nphi, seed):
     print(f"[case] fused {nr}x{nth}x{nphi} seed {seed}", flush=True)
