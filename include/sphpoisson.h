@@ -51,7 +51,7 @@ extern "C" {
 typedef SPP_ENUM(spp_status_e) {
     SPP_OK = 0,
     SPP_EINVAL = -1,     /* invalid argument (sizes, interfaces, NULL pointers) */
-    SPP_ENOTSUP = -2,    /* valid for the method, not supported by this build   */
+    SPP_ENOTSUP = -2,    /* valid for the method, not supported by the library */
     SPP_EDEVICE = -3,    /* a HIP call failed                                   */
     SPP_ENOMEM = -4,     /* host allocation failed                              */
     SPP_ESTATE = -5,     /* object used out of order (e.g. solve before upload) */
