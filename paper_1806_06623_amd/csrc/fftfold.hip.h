@@ -82,6 +82,10 @@ __global__ __launch_bounds__(THREADS, 4) void k_rfft_fwd_fold(const double* __re
         if (reset) reset += r;
     }
     spp_status_clear(reset, blk == 0);
+    // issue priority: high while a wave issues its loads, low through the
+    // transform, raised again for the stores, so that the waves of the other
+    // workgroup on the CU get their loads out while this one computes
+    __builtin_amdgcn_s_setprio(3);
     __shared__ c64 lds[2 * PB * LS];
     __shared__ c64 tws[N];
 
@@ -104,6 +108,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_rfft_fwd_fold(const double* __re
         for (int r = 0; r < 8; ++r) a[r] = src[16 * r];
         if (threadIdx.x < N) tws[threadIdx.x] = tw0;
         __syncthreads();   // twiddles
+        __builtin_amdgcn_s_setprio(0);
         // first pass of the line itself (radix 8, Ns = 1: butterfly c reads
         // points c + 16 r, no twiddles); the fold follows, the pass being linear
         c64 v[8];
@@ -167,6 +172,7 @@ __global__ __launch_bounds__(THREADS, 4) void k_rfft_fwd_fold(const double* __re
         out[size_t(N2 + p) * plane] = Xq.y;
     };
     c64 Xp, Xq;
+    __builtin_amdgcn_s_setprio(2);
     if (g == 0) {
         split(0, z[0][0], z[0][0], &Xp, &Xq);
         out[0] = Xp.x;                          // Re X_0
