@@ -420,6 +420,21 @@ __global__ __launch_bounds__(64 * NW) void k_proj_f32(const double* __restrict__
             if (s0 + 8 < KG) mfma_chunk_f32<RN, RM>(acc, pb, Bs, S::NP, s0 + 8, g, lr);
         }
 
+        // with ACCUM, every value of C the tile adds to is loaded before the
+        // first store, so that the loads are in flight together instead of
+        // each waiting behind the previous store
+        double prior[RM][RN][4];
+#pragma unroll
+        for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < RN; ++cb) {
+                const int col = cb * 16 + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rbase + rb * 16 + 4 * g + v;
+                    prior[rb][cb][v] = ACCUM && row < M && col < K ? Cq[size_t(row) * K + col] : 0.0;
+                }
+            }
 #pragma unroll
         for (int rb = 0; rb < RM; ++rb)
 #pragma unroll
@@ -429,9 +444,8 @@ __global__ __launch_bounds__(64 * NW) void k_proj_f32(const double* __restrict__
                 for (int v = 0; v < 4; ++v) {
                     const int row = rbase + rb * 16 + 4 * g + v;
                     if (row < M && col < K) {
-                        double* c = Cq + size_t(row) * K + col;
                         const double val = static_cast<double>(acc[rb][cb][v]);
-                        *c = ACCUM ? *c + val : val;
+                        Cq[size_t(row) * K + col] = ACCUM ? prior[rb][cb][v] + val : val;
                     }
                 }
             }

@@ -760,9 +760,15 @@ __device__ __forceinline__ unsigned long long block_absmax_bits(double v, bool n
     return out;
 }
 
-// r = s~ - L_q g for every element (q, i, j), FP64.  Workgroups (x, q) stride
-// over the plane of component q; each adds max |r| of its elements into
-// rmax_q[q] (and max |s~| into smax_q[q] when not NULL) with one atomic.
+// r = s~ - L_q g for every element (q, i, j), FP64.  Workgroup (x, q) covers
+// 256 (row chunk, j) columns of component q, a thread RES_ROWS consecutive
+// rows of one j: all its loads (the column with one row beyond each end, the
+// j -+ 1 neighbours, s~) are issued before the first result, so that about
+// 4 RES_ROWS loads are in flight per thread.  Each workgroup adds max |r| of
+// its elements into rmax_q[q] (and max |s~| into smax_q[q] when not NULL) with
+// one atomic.
+constexpr int RES_ROWS = 8;
+
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ St, const double* __restrict__ Gf,
                                                   const double* __restrict__ ob, const double* __restrict__ ib,
                                                   double* __restrict__ R, ResidualTables t, int nr, int nth,
@@ -772,35 +778,61 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ St,
     __shared__ double red[4];
     const int q = blockIdx.y;
     const int m = q <= nphi / 2 ? q : nphi - q;
-    const int plane = nr * nth;
+    const size_t plane = size_t(nr) * nth;
+    const int nchunks = (nr + RES_ROWS - 1) / RES_ROWS;
+    const int item = blockIdx.x * 256 + threadIdx.x;
     double mr = 0.0, ms = 0.0;
     bool nr_nan = false, ns_nan = false;
-    for (int el = blockIdx.x * 256 + threadIdx.x; el < plane; el += gridDim.x * 256) {
-        const int i = el / nth, j = el - i * nth;
-        const size_t e = size_t(q) * plane + el;
-        const double g0 = Gf[e];
-        // radial fluxes through the faces i+1/2 and i-1/2 (outer face: boundary
-        // term; inner face: the regular condition's term, 0 for zero flux)
-        double flux = 0.0;
-        if (i + 1 < nr) flux += t.alpha[i] * (Gf[e + nth] - g0);
-        else flux -= ob[size_t(q) * nth + j];
-        if (i > 0) flux -= t.alpha[i - 1] * (g0 - Gf[e - nth]);
-        else if (ib) flux -= ib[size_t(q) * nth + j];
-        const double Vi = t.V[i];
-        // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
-        double th = 0.0;
-        if (j + 1 < nth) th += t.sig[j + 1] * (Gf[e + 1] - g0);
-        if (j > 0) th -= t.sig[j] * (g0 - Gf[e - 1]);
-        const double Ri = t.VR[i] / Vi;
-        const double Lg = flux / Vi + Ri * (th / t.dmu[j] + t.Sj[j] * t.lamphi[m] * g0);
-        const double s = St[e];
-        const double r = s - Lg;
-        R[e] = r;
-        const double ar = __builtin_fabs(r), as = __builtin_fabs(s);
-        nr_nan |= ar != ar;
-        mr = ar > mr ? ar : mr;
-        ns_nan |= as != as;
-        ms = as > ms ? as : ms;
+    if (item < nth * nchunks) {
+        const int chunk = item / nth, j = item - chunk * nth;
+        const int i0 = chunk * RES_ROWS;
+        const double* __restrict__ G = Gf + size_t(q) * plane + j;
+        const double* __restrict__ Sq = St + size_t(q) * plane + j;
+        auto at = [&](int i) { return size_t(i < 0 ? 0 : (i < nr ? i : nr - 1)) * nth; };
+        // g of rows i0 - 1 .. i0 + RES_ROWS (clamped; the values past the ends are not used)
+        double c[RES_ROWS + 2], lj[RES_ROWS], rj[RES_ROWS], sv[RES_ROWS];
+#pragma unroll
+        for (int r = 0; r < RES_ROWS + 2; ++r) c[r] = G[at(i0 - 1 + r)];
+        const int dl = j > 0 ? -1 : 0, dr = j + 1 < nth ? 1 : 0;   // in-range neighbour offsets
+#pragma unroll
+        for (int r = 0; r < RES_ROWS; ++r) {
+            const size_t o = at(i0 + r);
+            lj[r] = G[o + dl];
+            rj[r] = G[o + dr];
+            sv[r] = Sq[o];
+        }
+        const double obj = i0 + RES_ROWS >= nr ? ob[size_t(q) * nth + j] : 0.0;
+        const double ibj = i0 == 0 && ib ? ib[size_t(q) * nth + j] : 0.0;
+        const double sig_l = t.sig[j], sig_h = t.sig[j + 1], dmu = t.dmu[j], sjl = t.Sj[j] * t.lamphi[m];
+#pragma unroll
+        for (int r = 0; r < RES_ROWS; ++r) {
+            const int i = i0 + r;
+            if (i < nr) {
+                const double g0 = c[r + 1];
+                // radial fluxes through the faces i+1/2 and i-1/2 (outer face:
+                // boundary term; inner face: the regular condition's term, 0
+                // for zero flux)
+                double flux = 0.0;
+                if (i + 1 < nr) flux += t.alpha[i] * (c[r + 2] - g0);
+                else flux -= obj;
+                if (i > 0) flux -= t.alpha[i - 1] * (g0 - c[r]);
+                else if (ib) flux -= ibj;
+                const double Vi = t.V[i];
+                // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
+                double th = 0.0;
+                if (j + 1 < nth) th += sig_h * (rj[r] - g0);
+                if (j > 0) th -= sig_l * (g0 - lj[r]);
+                const double Ri = t.VR[i] / Vi;
+                const double Lg = flux / Vi + Ri * (th / dmu + sjl * g0);
+                const double res = sv[r] - Lg;
+                R[size_t(q) * plane + size_t(i) * nth + j] = res;
+                const double ar = __builtin_fabs(res), as = __builtin_fabs(sv[r]);
+                nr_nan |= ar != ar;
+                mr = ar > mr ? ar : mr;
+                ns_nan |= as != as;
+                ms = as > ms ? as : ms;
+            }
+        }
     }
     const unsigned long long br = block_absmax_bits(mr, nr_nan, red);
     if (threadIdx.x == 0) atomicMax(rmax_q + q, br);
@@ -1111,7 +1143,7 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
     // per-component maxima start at zero (a fill kernel, capturable)
     const size_t npart = size_t(n_refine + 1) * nphi;
     hipLaunchKernelGGL(k_fill_u64, dim3((npart + 255) / 256), dim3(256), 0, s, part, npart);
-    const int rgx = std::min((nlines + 255) / 256, 8);
+    const int rgx = (nth * ((nr + RES_ROWS - 1) / RES_ROWS) + 255) / 256;
     for (int it = 0; it <= n_refine; ++it) {
         const double* src = St;
         if (it > 0) {
