@@ -304,7 +304,12 @@ __global__ __launch_bounds__(THREADS, 3) void k_momentum(const double* __restric
 // components (the row's Phi having been exchanged in the previous row's
 // step), and after the phi-faces.  Phi is double-buffered in LDS by row.
 // Threads past the end of the plane (a last workgroup with whole rows past
-// N_theta) take part in the barriers and store nothing.
+// N_theta; PARTIAL launches only) take part in the barriers and store nothing.
+// The row loop is unrolled and reads its per-row factors from LDS, and with
+// PARTIAL = false the stores are unconditional: the only global loads after
+// the prologue are the rows of Phi, so that waiting for them never waits for
+// a store as well.
+template <bool PARTIAL>
 __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restrict__ phi,
                                                            const double* __restrict__ tout, double* __restrict__ fx,
                                                            double* __restrict__ fy, double* __restrict__ fz, Tables t,
@@ -314,6 +319,9 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
     __shared__ double sphi[2][3][THREADS];   // Phi of row i (buffer i % 2) at theta rows j-1, j, j+1, per cell
     __shared__ double scomp[2][THREADS];     // radial and theta centred components of the current row, per cell
     __shared__ double sface[3][THREADS];     // the upper phi-face's stress vector, per cell
+    // per-row factors of the chunk, rows i0 .. i0 + ROWS_LDS (clamped):
+    // 1/r_i, 1/dr of face i + 1/2, the ring factor of row i, r^2 of face i + 1/2
+    __shared__ double srow[4][ROWS_LDS + 1];
     const int plane = nth * nphi;
     const int chunk = blockIdx.x / gx;
     const int tid = threadIdx.x;
@@ -329,6 +337,12 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
     const int col[3] = {jm * nphi + ec, j * nphi + ec, jp * nphi + ec};
     const int i0 = chunk * ROWS_LDS;
     const int i1 = i0 + ROWS_LDS < nr ? i0 + ROWS_LDS : nr;
+    if (tid < 4 * (ROWS_LDS + 1)) {
+        const int a = tid / (ROWS_LDS + 1), ii = i0 + tid - a * (ROWS_LDS + 1);
+        const int c0 = ii < nr ? ii : nr - 1, c1 = ii + 1 < nr ? ii + 1 : nr;
+        srow[a][tid - a * (ROWS_LDS + 1)] =
+            a == 0 ? t.invr[c0] : a == 1 ? t.invdr[c1] : a == 2 ? t.ring[c0] : t.R2[c1];
+    }
 
     const double jck = t.jc[ec], jsk = t.js[ec], c1 = t.cp1[ec], s1 = t.sp1[ec];
     const double S2 = t.is2[j], SC = t.isc[j], SN = t.is[j], CS = t.ic[j], D = t.dth[j];
@@ -346,11 +360,10 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
 #pragma unroll
         for (int a = 0; a < 3; ++a) sphi[i & 1][a][tid] = v[a];
     };
-    // the own column's theta and phi centred components of row i from its
-    // column values v and the neighbours' published ones
-    auto own_tp = [&](int i, const double (&v)[3], double& ct, double& cp, double& gtl, double& gth, double& gpl,
-                      double& gph) {
-        const double ir = t.invr[i];
+    // the own column's theta and phi centred components of row i (ir = 1/r_i)
+    // from its column values v and the neighbours' published ones
+    auto own_tp = [&](int i, double ir, const double (&v)[3], double& ct, double& cp, double& gtl, double& gth,
+                      double& gpl, double& gph) {
         gtl = (v[1] - v[0]) * (ir * qtl);
         gth = (v[2] - v[1]) * (ir * qth);
         ct = avg(gtl, gth);
@@ -359,16 +372,20 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
         gph = (sphi[i & 1][1][rn] - v[1]) * rp;
         cp = avg(gpl, gph);
     };
-    // radial quotients of face i + 1/2 at the three columns (the outer face:
-    // the extrapolated derivative)
-    auto rquot = [&](int i, const double (&v)[3], const double (&w)[3], double (&g)[3]) {
+    // radial quotients of face i + 1/2 at the three columns (f = its 1/dr;
+    // the outer face: the extrapolated derivative, from to[])
+    double to[3] = {0.0, 0.0, 0.0};
+    if (i1 == nr) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) to[a] = tout[col[a]];
+    }
+    auto rquot = [&](int i, double f, const double (&v)[3], const double (&w)[3], double (&g)[3]) {
         if (i + 1 < nr) {
-            const double f = t.invdr[i + 1];
 #pragma unroll
             for (int a = 0; a < 3; ++a) g[a] = (w[a] - v[a]) * f;
         } else {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) g[a] = -tout[col[a]] * inv_ro2;
+            for (int a = 0; a < 3; ++a) g[a] = -to[a] * inv_ro2;
         }
     };
 
@@ -388,11 +405,11 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
 #pragma unroll
         for (int a = 0; a < 3; ++a) grl[a] = (cur[a] - prev[a]) * f;
         double ct0, cp0, x0, x1, x2, x3;
-        own_tp(i0, cur, ct0, cp0, x0, x1, x2, x3);
+        own_tp(i0, t.invr[i0], cur, ct0, cp0, x0, x1, x2, x3);
         double g1 = ct0, g2 = cp0;
         if (i0 > 0) {
             double ctb, cpb;
-            own_tp(i0 - 1, prev, ctb, cpb, x0, x1, x2, x3);
+            own_tp(i0 - 1, t.invr[i0 - 1], prev, ctb, cpb, x0, x1, x2, x3);
             g1 = avg(ctb, ct0);
             g2 = avg(cpb, cp0);
         }
@@ -401,19 +418,22 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
     }
     __syncthreads();   // the buffer of row i0 - 1 is rewritten with row i0 + 1 below
 
-    for (int i = i0; i < i1; ++i) {
+#pragma unroll
+    for (int r = 0; r < ROWS_LDS; ++r) {
+        const int i = i0 + r;
+        if (i >= i1) break;
         double nn[3];
         column(i + 2, nn);    // in flight through this row
         publish(i + 1, nxt);
         // row i: radial components at the three columns, theta and phi ones
         // of the own column, phi ones of the columns j -+ 1
         double grh[3], cr[3], cp[3];
-        rquot(i, cur, nxt, grh);
+        rquot(i, srow[1][r], cur, nxt, grh);
 #pragma unroll
         for (int a = 0; a < 3; ++a) cr[a] = avg(grl[a], grh[a]);
         double ct, gtl, gth, gpl, gph;
-        own_tp(i, cur, ct, cp[1], gtl, gth, gpl, gph);
-        const double ir = t.invr[i];
+        const double ir = srow[0][r];
+        own_tp(i, ir, cur, ct, cp[1], gtl, gth, gpl, gph);
 #pragma unroll
         for (int a = 0; a < 3; a += 2) {
             const double rp = ir * qp[a];
@@ -423,7 +443,7 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
         scomp[1][tid] = ct;
         __syncthreads();
 
-        const double sr = k4 * t.ring[i], hsr = 0.5 * sr;
+        const double sr = k4 * srow[2][r], hsr = 0.5 * sr;
         // upper phi-face k + 1/2, evaluated here once
         const V3 upp = pvec(scalars(gph, avg(cr[1], scomp[0][rn]), avg(ct, scomp[1][rn]), sr, hsr), D, SN, CS, c1, s1);
         sface[0][tid] = upp.x;
@@ -439,17 +459,17 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
         double g1 = ct, g2 = cp[1];
         if (i + 1 < nr) {
             double ctn, cpn, x0, x1, x2, x3;
-            own_tp(i + 1, nxt, ctn, cpn, x0, x1, x2, x3);
+            own_tp(i + 1, srow[0][r + 1], nxt, ctn, cpn, x0, x1, x2, x3);
             g1 = avg(ct, ctn);
             g2 = avg(cp[1], cpn);
         }
-        const double srr = k4 * t.R2[i + 1];
+        const double srr = k4 * srow[3][r];
         const V3 upr = rvec(scalars(grh[1], g1, g2, srr, 0.5 * srr), S2, SC, SN, jck, jsk, dphi);
         __syncthreads();
 
         // lower phi-face k - 1/2: the cell k - 1's upper one
         const V3 lowp{sface[0][ln], sface[1][ln], sface[2][ln]};
-        if (valid) {
+        if (!PARTIAL || valid) {
             const size_t o = size_t(i) * plane + e;
             __builtin_nontemporal_store(-(((upr.x - lowr.x) + (upt.x - lowt.x)) + (upp.x - lowp.x)), fx + o);
             __builtin_nontemporal_store(-(((upr.y - lowr.y) + (upt.y - lowt.y)) + (upp.y - lowp.y)), fy + o);

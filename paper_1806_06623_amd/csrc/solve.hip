@@ -801,32 +801,55 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ St,
             rj[r] = G[o + dr];
             sv[r] = Sq[o];
         }
+        // the row tables of the chunk, also loaded up front (al[r] = alpha of
+        // row i0 - 1 + r), so that no row waits on a load
+        double al[RES_ROWS + 1], vv[RES_ROWS], vrr[RES_ROWS];
+#pragma unroll
+        for (int r = 0; r <= RES_ROWS; ++r) {
+            const int i = i0 - 1 + r;
+            al[r] = t.alpha[i < 0 ? 0 : (i < nr ? i : nr - 1)];
+        }
+#pragma unroll
+        for (int r = 0; r < RES_ROWS; ++r) {
+            const int i = i0 + r < nr ? i0 + r : nr - 1;
+            vv[r] = t.V[i];
+            vrr[r] = t.VR[i];
+        }
         const double obj = i0 + RES_ROWS >= nr ? ob[size_t(q) * nth + j] : 0.0;
         const double ibj = i0 == 0 && ib ? ib[size_t(q) * nth + j] : 0.0;
         const double sig_l = t.sig[j], sig_h = t.sig[j + 1], dmu = t.dmu[j], sjl = t.Sj[j] * t.lamphi[m];
+        // every load is awaited here, once: the rows below store between
+        // their computations, and a wait for a later row's load would
+        // otherwise also wait for the stores issued before it
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt not waited
+        double res[RES_ROWS];
+#pragma unroll
+        for (int r = 0; r < RES_ROWS; ++r) {
+            const int i = i0 + r;
+            const double g0 = c[r + 1];
+            // radial fluxes through the faces i+1/2 and i-1/2 (outer face:
+            // boundary term; inner face: the regular condition's term, 0 for
+            // zero flux)
+            double flux = 0.0;
+            if (i + 1 < nr) flux += al[r + 1] * (c[r + 2] - g0);
+            else flux -= obj;
+            if (i > 0) flux -= al[r] * (g0 - c[r]);
+            else if (ib) flux -= ibj;
+            const double Vi = vv[r];
+            // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
+            double th = 0.0;
+            if (j + 1 < nth) th += sig_h * (rj[r] - g0);
+            if (j > 0) th -= sig_l * (g0 - lj[r]);
+            const double Ri = vrr[r] / Vi;
+            const double Lg = flux / Vi + Ri * (th / dmu + sjl * g0);
+            res[r] = sv[r] - Lg;
+        }
 #pragma unroll
         for (int r = 0; r < RES_ROWS; ++r) {
             const int i = i0 + r;
             if (i < nr) {
-                const double g0 = c[r + 1];
-                // radial fluxes through the faces i+1/2 and i-1/2 (outer face:
-                // boundary term; inner face: the regular condition's term, 0
-                // for zero flux)
-                double flux = 0.0;
-                if (i + 1 < nr) flux += t.alpha[i] * (c[r + 2] - g0);
-                else flux -= obj;
-                if (i > 0) flux -= t.alpha[i - 1] * (g0 - c[r]);
-                else if (ib) flux -= ibj;
-                const double Vi = t.V[i];
-                // theta fluxes (pole faces have sigma = 0) and the phi eigenvalue term
-                double th = 0.0;
-                if (j + 1 < nth) th += sig_h * (rj[r] - g0);
-                if (j > 0) th -= sig_l * (g0 - lj[r]);
-                const double Ri = t.VR[i] / Vi;
-                const double Lg = flux / Vi + Ri * (th / dmu + sjl * g0);
-                const double res = sv[r] - Lg;
-                R[size_t(q) * plane + size_t(i) * nth + j] = res;
-                const double ar = __builtin_fabs(res), as = __builtin_fabs(sv[r]);
+                R[size_t(q) * plane + size_t(i) * nth + j] = res[r];
+                const double ar = __builtin_fabs(res[r]), as = __builtin_fabs(sv[r]);
                 nr_nan |= ar != ar;
                 mr = ar > mr ? ar : mr;
                 ns_nan |= as != as;
@@ -1249,7 +1272,10 @@ spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G,
     // theta row
     if (nphi >= 64 && momentum::THREADS % nphi == 0) {
         const int lchunks = (nr + momentum::ROWS_LDS - 1) / momentum::ROWS_LDS;
-        hipLaunchKernelGGL(momentum::k_momentum_rows, dim3(gx * lchunks), dim3(momentum::THREADS), 0, s, phi, B, fx,
+        // whole workgroups only (every thread on a cell) unless the plane ends mid-workgroup
+        auto kern = (nth * nphi) % momentum::THREADS == 0 ? momentum::k_momentum_rows<false>
+                                                          : momentum::k_momentum_rows<true>;
+        hipLaunchKernelGGL(kern, dim3(gx * lchunks), dim3(momentum::THREADS), 0, s, phi, B, fx,
                            fy, fz, t, nr, nth, nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
     } else {
         auto kern = nphi % 64 == 0 ? momentum::k_momentum<true> : momentum::k_momentum<false>;
