@@ -80,14 +80,14 @@ def stage_model(nr, nth, nphi, parity, fused):
 TRAFFIC = {
     "modal::k_modal": {"grid": (550, 128, 256),
                        "sources": ("modal.hip.h", "modal_layout.h", "radial.hip.h", "status.h", "solve.hip"),
-                       "source_digest": "eb0e15adaedc0266",
-                       "bytes_per_launch": (81364.7 * 2.0 + 140806.0) * 1024.0},
+                       "source_digest": "21caead8444a8669",
+                       "bytes_per_launch": (81373.2 * 2.0 + 140806.0) * 1024.0},
     "faceflux::k_face_fluxes": {"grid": (550, 128, 256), "sources": ("fluxes.hip.h", "xcd.h", "solve.hip"),
-                                "source_digest": "9a0394310cbe7022",
-                                "bytes_per_launch": (74480.2 * 2.0 + 422617.3) * 1024.0},
+                                "source_digest": "275d2b8480a65ffe",
+                                "bytes_per_launch": (74474.1 * 2.0 + 422605.1) * 1024.0},
     "momentum::k_momentum_rows": {"grid": (550, 128, 256), "sources": ("momentum.hip.h", "xcd.h", "solve.hip"),
-                                  "source_digest": "0a1c0fa397914e78",
-                                  "bytes_per_launch": (78458.8 * 2.0 + 422400.1) * 1024.0},
+                                  "source_digest": "8bfea88ec10d9dfb",
+                                  "bytes_per_launch": (78510.8 * 2.0 + 422400.2) * 1024.0},
 }
 
 
