@@ -81,6 +81,8 @@ def _gpu_forces(plan, phi, G):
     (5, 2, 4, 0.0, "uniform", "random"),
     (20, 24, 128, 0.0, "uniform", "random"),     # two theta rows per workgroup
     (12, 10, 512, 1.5, "skewed", "random"),      # a theta row across two workgroups
+    (11, 7, 128, 0.0, "skewed", "random"),       # whole-row workgroups, the last one half past the plane
+    (10, 6, 64, 1.5, "uniform", "random"),       # four rows per workgroup, the last workgroup half full
 ])
 def test_momentum_matches_oracle(nr, nth, nphi, r0, theta, field):
     import paper_1806_06623_amd as spp
