@@ -150,10 +150,18 @@ __global__ __launch_bounds__(64 * NW) void k_proj_f64(const double* __restrict__
         for (int s0 = 0; s0 < KG; s0 += 16) {
             const int s1 = s0 + 8 < KG ? s0 + 8 : KG - 8;
             load_chunk<RM, KVEC>(pb, Aq, M, K, rbase, lr, kb0 + s1);
+            __builtin_amdgcn_sched_barrier(0);
             mfma_chunk<RN, RM>(acc, pa, Bs, S::NP, s0, g, lr);
             const int s2 = s0 + 16 < KG ? s0 + 16 : KG - 8;
+            __builtin_amdgcn_sched_barrier(0);
             load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0 + s2);
-            if (s0 + 8 < KG) mfma_chunk<RN, RM>(acc, pb, Bs, S::NP, s0 + 8, g, lr);
+            __builtin_amdgcn_sched_barrier(0);
+            const bool hb = s0 + 8 < KG;
+#pragma unroll
+            for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pb[rb][u] = hb ? pb[rb][u] : 0.0;
+            mfma_chunk<RN, RM>(acc, pb, Bs, S::NP, hb ? s0 + 8 : s0, g, lr);
         }
 
 #pragma unroll
@@ -299,10 +307,21 @@ __global__ __launch_bounds__(64 * NW) void k_proj_par(const double* __restrict__
         for (int s0 = 0; s0 < KG; s0 += 16) {
             const int s1 = s0 + 8 < KG ? s0 + 8 : KG - 8;
             load_chunk_par<RM, KVEC, FWD>(xb, zb, Aq, M, N, h, rbase, lr, kb0 + s1);
+            __builtin_amdgcn_sched_barrier(0);
             mfma_chunk_par<RN, RM, FWD>(ae, ao, xa, za, Be, Bo, S::NP, s0, g, lr);
             const int s2 = s0 + 16 < KG ? s0 + 16 : KG - 8;
+            __builtin_amdgcn_sched_barrier(0);
             load_chunk_par<RM, KVEC, FWD>(xa, za, Aq, M, N, h, rbase, lr, kb0 + s2);
-            if (s0 + 8 < KG) mfma_chunk_par<RN, RM, FWD>(ae, ao, xb, zb, Be, Bo, S::NP, s0 + 8, g, lr);
+            __builtin_amdgcn_sched_barrier(0);
+            const bool hb = s0 + 8 < KG;
+#pragma unroll
+            for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    xb[rb][u] = hb ? xb[rb][u] : 0.0;
+                    zb[rb][u] = hb ? zb[rb][u] : 0.0;
+                }
+            mfma_chunk_par<RN, RM, FWD>(ae, ao, xb, zb, Be, Bo, S::NP, hb ? s0 + 8 : s0, g, lr);
         }
 
 #pragma unroll
@@ -413,11 +432,23 @@ __global__ __launch_bounds__(64 * NW) void k_proj_f32(const double* __restrict__
         if (gi != blockIdx.x * NW + wave) load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0);
         for (int s0 = 0; s0 < KG; s0 += 16) {
             const int s1 = s0 + 8 < KG ? s0 + 8 : KG - 8;
+            // the loads of the next chunk are pinned ahead of this chunk's
+            // products (scheduling barriers), and the second product is
+            // unconditional (zeroed when past K): otherwise the compiler sinks
+            // each 16-byte load next to its FP32 conversion and waits on it there
             load_chunk<RM, KVEC>(pb, Aq, M, K, rbase, lr, kb0 + s1);
+            __builtin_amdgcn_sched_barrier(0);
             mfma_chunk_f32<RN, RM>(acc, pa, Bs, S::NP, s0, g, lr);
             const int s2 = s0 + 16 < KG ? s0 + 16 : KG - 8;
+            __builtin_amdgcn_sched_barrier(0);
             load_chunk<RM, KVEC>(pa, Aq, M, K, rbase, lr, kb0 + s2);
-            if (s0 + 8 < KG) mfma_chunk_f32<RN, RM>(acc, pb, Bs, S::NP, s0 + 8, g, lr);
+            __builtin_amdgcn_sched_barrier(0);
+            const bool hb = s0 + 8 < KG;
+#pragma unroll
+            for (int rb = 0; rb < RM; ++rb)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) pb[rb][u] = hb ? pb[rb][u] : 0.0;
+            mfma_chunk_f32<RN, RM>(acc, pb, Bs, S::NP, hb ? s0 + 8 : s0, g, lr);
         }
 
         // with ACCUM, every value of C the tile adds to is loaded before the
