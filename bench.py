@@ -11,7 +11,7 @@ inverse FFT.  Inputs are resident in HBM before the timed region.
 Order of a run: set-up; the first solves after process start, timed as they
 come (``cold_start``: the GPU's clocks are still ramping); a settling period
 of back-to-back solves; the other legs (mixed form, face fluxes, momentum
-source, a device copy of one field as the practical HBM rate, batched and
+source, residual, copies of one field as the bandwidth reference, batched and
 served solves); another settling period (``settle``), the W warm-up solves
 and the K timed ones (``value``), the latency loop and the per-stage profile;
 finally the FP64 oracle timed on the host CPU.
@@ -293,6 +293,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-fluxes", action="store_true")
     ap.add_argument("--no-momentum", action="store_true")
+    ap.add_argument("--no-residual", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--n-refine", type=int, default=1)
@@ -446,6 +447,29 @@ def main():
         log(f"momentum source: {ms * 1e3:.1f} us per call, {mom['GBps']} GB/s")
         del F
 
+    # the FP64 residual 4 pi G rho - L Phi (spp_residual) of the same Phi: rho
+    # and Phi read once, r written, HBM-bound
+    resid = None
+    if not args.no_residual:
+        R = torch.empty_like(phi)
+        for _ in range(20):
+            plan.residual(rho, phi, G=case["G"], out=R)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            plan.residual(rho, phi, G=case["G"], out=R)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        rbytes = 3 * 8.0 * zones
+        resid = {"ms": round(ms, 5), "alg_bytes": rbytes, "GBps": round(rbytes / (ms * 1e-3) / 1e9, 1),
+                 "hbm_frac": round(rbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "note": "whole entry point: outer-shell boundary term (shell FFT, per-mode beta, inverse FFT) "
+                         "and the flux stencil; algorithmic bytes = rho and Phi read once + r written"}
+        log(f"residual: {ms * 1e3:.1f} us per call, {resid['GBps']} GB/s")
+        del R
+
     # copies of one field from five distinct sources (so that none is read
     # from the last-level cache): torch's device copy (`hbm_copy`; its
     # FETCH_SIZE/WRITE_SIZE counters calibrate the traffic figures) and the
@@ -558,7 +582,7 @@ def main():
 
     # memory-bound figures against the streaming copy's rate as well
     if stream is not None:
-        for d in [v for k, v in stages.items() if k != "fused_modal"] + [face, mom]:
+        for d in [v for k, v in stages.items() if k != "fused_modal"] + [face, mom, resid]:
             if d is not None:
                 d["stream_frac"] = round(d["GBps"] / stream["GBps"], 4)
     if mixed is not None:
@@ -582,6 +606,7 @@ def main():
         "mixed": mixed,
         "face_fluxes": face,
         "momentum_source": mom,
+        "residual": resid,
         "hbm_copy": copy,
         "hbm_stream": stream,
         "batched": batch,

@@ -950,14 +950,31 @@ __global__ __launch_bounds__(256) void k_residual_phys(const double* __restrict_
     const double to = i0 + RROWS >= nr ? tout[e] : 0.0;
     const double ti = (i0 == 0 && tin) ? tin[e] : 0.0;
     const double sp = t.sig[j + 1], sm = t.sig[j], idm = 1.0 / t.dmu[j], sj = t.Sj[j] * inv_dphi2;
+    // the chunk's row tables, loaded up front too (al[u] = alpha of row i0 - 1 + u)
+    double al[RROWS + 1], vv[RROWS], vrr[RROWS];
+#pragma unroll
+    for (int u = 0; u <= RROWS; ++u) {
+        const int i = i0 - 1 + u;
+        al[u] = t.alpha[i < 0 ? 0 : (i < nr ? i : nr - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < RROWS; ++u) {
+        const int i = i0 + u < nr ? i0 + u : nr - 1;
+        vv[u] = t.V[i];
+        vrr[u] = t.VR[i];
+    }
+    // every load is awaited here, once: the rows below store between their
+    // computations, and a wait for a later row's load would otherwise also wait
+    // for the stores issued before it
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt not waited
 #pragma unroll
     for (int u = 0; u < RROWS; ++u) {
         const int i = i0 + u;
         if (i < nr) {
             const double x = c[u + 1];
-            const double fo = i + 1 < nr ? t.alpha[i] * (c[u + 2] - x) : -to;
-            const double fi = i > 0 ? t.alpha[i - 1] * (x - c[u]) : ti;
-            const double Vi = t.V[i], Ri = t.VR[i] / Vi;
+            const double fo = i + 1 < nr ? al[u + 1] * (c[u + 2] - x) : -to;
+            const double fi = i > 0 ? al[u] * (x - c[u]) : ti;
+            const double Vi = vv[u], Ri = vrr[u] / Vi;
             const double th = sp * (jp[u] - x) - sm * (x - jm[u]);
             const double LP = (fo - fi) / Vi + Ri * (th * idm + sj * (kp[u] - 2.0 * x + km[u]));
             r[size_t(i) * plane + e] = four_pi_g * src[u] - LP;
