@@ -917,6 +917,7 @@ __global__ __launch_bounds__(256) void k_refine_gate(spp_status_record* __restri
 // neighbour rows come from cache (adjacent threads load them; plane blocks in
 // the XCD-aware order of spp_plane_block).
 constexpr int RROWS = 4;
+constexpr int RES_LDS_ROWS = 8;   // rows per thread of k_residual_rows
 
 __global__ __launch_bounds__(256) void k_residual_phys(const double* __restrict__ rho, const double* __restrict__ phi,
                                                        const double* __restrict__ tout,
@@ -979,6 +980,82 @@ __global__ __launch_bounds__(256) void k_residual_phys(const double* __restrict_
             const double LP = (fo - fi) / Vi + Ri * (th * idm + sj * (kp[u] - 2.0 * x + km[u]));
             r[size_t(i) * plane + e] = four_pi_g * src[u] - LP;
         }
+    }
+}
+
+// The same residual for N_phi dividing 256: every workgroup covers whole theta
+// rows, so the phi neighbours of a value are values other threads of the
+// workgroup have loaded.  They are exchanged through LDS instead of loaded
+// again, and the per-row factors (alpha, 1/V_i and R_i = (VR)_i / V_i) are
+// formed once per workgroup.  Threads past the plane (whole theta rows of
+// the last workgroup) load a valid row, take part in the exchange among
+// themselves and store nothing.  r is stored non-temporally (nothing here
+// reads it), so that it does not evict the rows of Phi and rho that the
+// neighbouring workgroups still read.
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_residual_rows(const double* __restrict__ rho, const double* __restrict__ phi,
+                                                       const double* __restrict__ tout,
+                                                       const double* __restrict__ tin, double* __restrict__ r,
+                                                       ResidualTables t, double four_pi_g, int nr, int nth,
+                                                       int nphi, double inv_dphi2, int gx)
+{
+    __shared__ double cs[ROWS][256];     // this workgroup's Phi values of its ROWS rows
+    __shared__ double fa[3][ROWS + 1];   // alpha of row i0 - 1 + u; 1/V and R of row i0 + u
+    const int tid = threadIdx.x;
+    const int plane = nth * nphi;
+    const int chunk = blockIdx.x / gx;
+    const int e = spp_plane_block(blockIdx.x - chunk * gx, gx) * 256 + tid;
+    const bool live = e < plane;
+    const int jj = e / nphi, k = e - jj * nphi;
+    const int j = jj < nth ? jj : nth - 1;
+    const int el = j * nphi + k;
+    const int ejp = j + 1 < nth ? el + nphi : el;      // pole faces: sigma = 0
+    const int ejm = j > 0 ? el - nphi : el;
+    const int tkp = k + 1 < nphi ? tid + 1 : tid + 1 - nphi;
+    const int tkm = k > 0 ? tid - 1 : tid - 1 + nphi;
+    const int i0 = chunk * ROWS;
+    auto clampr = [&](int i) { return i < 0 ? 0 : (i < nr ? i : nr - 1); };
+    double c[ROWS + 2], jp[ROWS], jm[ROWS], src[ROWS];
+#pragma unroll
+    for (int u = 0; u < ROWS + 2; ++u) c[u] = phi[size_t(clampr(i0 - 1 + u)) * plane + el];
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) {
+        const size_t b = size_t(clampr(i0 + u)) * plane;
+        jp[u] = phi[b + ejp];
+        jm[u] = phi[b + ejm];
+        src[u] = rho[b + el];
+    }
+    const double to = i0 + ROWS >= nr ? tout[el] : 0.0;
+    const double ti = (i0 == 0 && tin) ? tin[el] : 0.0;
+    const double sp = t.sig[j + 1], sm = t.sig[j], dm = t.dmu[j], sjv = t.Sj[j];
+    double fal = 0.0, fv = 1.0, fvr = 0.0;
+    if (tid <= ROWS) {
+        fal = t.alpha[clampr(i0 - 1 + tid)];
+        fv = t.V[clampr(i0 + tid)];
+        fvr = t.VR[clampr(i0 + tid)];
+    }
+    // every load is awaited here, once, before any store
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt not waited
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) cs[u][tid] = c[u + 1];
+    if (tid <= ROWS) {
+        const double iv = 1.0 / fv;
+        fa[0][tid] = fal;
+        fa[1][tid] = iv;
+        fa[2][tid] = fvr * iv;
+    }
+    const double idm = 1.0 / dm, sj = sjv * inv_dphi2;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) {
+        const int i = i0 + u;
+        const double x = c[u + 1];
+        const double fo = i + 1 < nr ? fa[0][u + 1] * (c[u + 2] - x) : -to;
+        const double fi = i > 0 ? fa[0][u] * (x - c[u]) : ti;
+        const double th = sp * (jp[u] - x) - sm * (x - jm[u]);
+        const double ph = cs[u][tkp] - 2.0 * x + cs[u][tkm];
+        const double LP = (fo - fi) * fa[1][u] + fa[2][u] * (th * idm + sj * ph);
+        if (live && i < nr) __builtin_nontemporal_store(four_pi_g * src[u] - LP, r + size_t(i) * plane + el);
     }
 }
 
@@ -1332,10 +1409,17 @@ spp_status spp_launch_residual(const spp_plan_s* p, const double* rho, const dou
     if (p->inner_regular) shell_term(phi, T.d(L.gamma), C, D);
     const ResidualTables rt{T.d(L.alpha), T.d(L.V), T.d(L.VR), T.d(L.sig), T.d(L.dmu), T.d(L.Sj), T.d(L.lamphi)};
     const int gx = (plane + 255) / 256;
-    const int chunks = (nr + RROWS - 1) / RROWS;
     const double dphi = 2.0 * M_PI / nphi;
-    hipLaunchKernelGGL(k_residual_phys, dim3(gx * chunks), dim3(256), 0, s, rho, phi, B,
-                       p->inner_regular ? D : nullptr, r, rt, 4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
+    const double* tin = p->inner_regular ? D : nullptr;
+    if (256 % nphi == 0) {
+        const int chunks = (nr + RES_LDS_ROWS - 1) / RES_LDS_ROWS;
+        hipLaunchKernelGGL(k_residual_rows<RES_LDS_ROWS>, dim3(gx * chunks), dim3(256), 0, s, rho, phi, B, tin, r, rt,
+                           4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
+    } else {
+        const int chunks = (nr + RROWS - 1) / RROWS;
+        hipLaunchKernelGGL(k_residual_phys, dim3(gx * chunks), dim3(256), 0, s, rho, phi, B, tin, r, rt,
+                           4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_residual: ") + hipGetErrorString(e));
     return SPP_OK;

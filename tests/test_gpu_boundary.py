@@ -33,6 +33,7 @@ def _random_case(nr, nth, nphi, seed, r0=0.0, theta="uniform"):
     (9, 70, 32, 0.0, "skewed", "auto"),
     (24, 16, 16, 2.0, "coarsened", "zero_flux"),
     (24, 16, 16, 2.0, "coarsened", "regular"),
+    (7, 6, 512, 1.0, "uniform", "regular"),   # N_phi > 256: the per-column kernel
     (550, 128, 256, 0.0, "uniform", "auto"),
 ])
 def test_residual_matches_oracle(nr, nth, nphi, r0, theta, inner):
