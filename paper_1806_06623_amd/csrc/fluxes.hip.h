@@ -29,7 +29,7 @@ namespace faceflux {
 
 constexpr int THREADS = 256;
 constexpr int ROWS = 8;    // radial rows per thread (k_face_fluxes)
-constexpr int BATCH = 16;  // matrix loads in flight per thread (k_outer_coef, k_outer_apply)
+constexpr int BATCH = 16;  // matrix loads in flight per thread (k_shell_apply)
 
 struct Tables {
     const double* alpha;   // [N_r], alpha[N_r - 1] = 0
@@ -87,18 +87,18 @@ __global__ __launch_bounds__(THREADS) void k_face_fluxes(const double* __restric
     }
 }
 
-// Outer boundary term of Sec. 3.2 on the outermost shell, per Fourier mode m:
-//   ob_q = H_m diag(beta_m) H_m^T D g_q
-// for the components q = m and q = N_phi - m of m (one component for m = 0
-// and m = N_phi / 2).  With W_m = H_m^T D, i.e. H_m = diag(1/dmu) W_m^T:
-//   k_outer_coef   c_l  = beta_l sum_j H[j][l] dmu_j g_j
-//   k_outer_apply  ob_j = (1/dmu_j) sum_l W[l][j] c_l
-// Each is a product with the transpose of a stored N_theta x N_theta matrix;
-// workgroup (m, b) computes the 32 outputs 32 b .. 32 b + 31 of both
-// components of m from one pass over 32 columns of the matrix, so the
-// (N_phi/2 + 1) x ceil(N_theta/32) workgroups share the matrix bytes.
-// Vectors are [q][N_theta] (g_q may be strided: g + q gq).  Dynamic LDS:
-// (2 N_theta + 512) doubles.
+// Boundary term of Sec. 3.2 on a shell, per Fourier mode m:
+//   ob_q = H_m diag(c_m) H_m^T D g_q
+// (c = beta on the outermost shell; c = gamma on the innermost one with the
+// regular inner condition) for the components q = m and q = N_phi - m of m
+// (one component for m = 0 and m = N_phi / 2).  The plan stores each
+// B_m = H_m diag(c_m) H_m^T D as one N_theta x N_theta matrix, transposed, so
+// that k_shell_apply forms ob_q = B_m g_q in one product; workgroup (m, b)
+// computes the 32 outputs 32 b .. 32 b + 31 of both components of m from one
+// pass over 32 columns of the stored matrix, so the (N_phi/2 + 1) x
+// ceil(N_theta/32) workgroups share the matrix bytes.  Vectors are
+// [q][N_theta] (g_q may be strided: g + q gq).  Dynamic LDS: (2 N_theta +
+// 512) doubles.
 
 // y = A^T x for the 32 outputs o0 .. o0 + 31 and two vectors x0, x1 (LDS):
 // thread (o, sp) = (tid % 32, tid / 32) sums the rows x = sp, sp + 8, ...
@@ -137,10 +137,9 @@ __device__ __forceinline__ void cols32(const double* __restrict__ A, const doubl
     }
 }
 
-__global__ __launch_bounds__(256) void k_outer_coef(const double* __restrict__ g, size_t gq,
-                                                    double* __restrict__ c, const double* __restrict__ H,
-                                                    const double* __restrict__ beta,
-                                                    const double* __restrict__ dmu, int nth, int nphi)
+__global__ __launch_bounds__(256) void k_shell_apply(const double* __restrict__ g, size_t gq,
+                                                     double* __restrict__ ob, const double* __restrict__ B, int nth,
+                                                     int nphi)
 {
     extern __shared__ double sh[];
     double* x0 = sh;
@@ -149,53 +148,26 @@ __global__ __launch_bounds__(256) void k_outer_coef(const double* __restrict__ g
     const bool two = m > 0 && 2 * m < nphi;
     const int q1 = nphi - m;
     for (int j = threadIdx.x; j < nth; j += 256) {
-        x0[j] = g[size_t(m) * gq + j] * dmu[j];
-        x1[j] = two ? g[size_t(q1) * gq + j] * dmu[j] : 0.0;
+        x0[j] = g[size_t(m) * gq + j];
+        x1[j] = two ? g[size_t(q1) * gq + j] : 0.0;
     }
     __syncthreads();
     double y0, y1;
-    cols32(H + size_t(m) * nth * nth, x0, x1, o0, nth, sh + 2 * nth, y0, y1);
-    const int l = o0 + int(threadIdx.x);
-    if (threadIdx.x < 32 && l < nth) {
-        const double b = beta[size_t(m) * nth + l];
-        c[size_t(m) * nth + l] = y0 * b;
-        if (two) c[size_t(q1) * nth + l] = y1 * b;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_outer_apply(const double* __restrict__ c, double* __restrict__ ob,
-                                                     const double* __restrict__ W,
-                                                     const double* __restrict__ dmu, int nth, int nphi)
-{
-    extern __shared__ double sh[];
-    double* x0 = sh;
-    double* x1 = sh + nth;
-    const int m = blockIdx.x, o0 = blockIdx.y * 32;
-    const bool two = m > 0 && 2 * m < nphi;
-    const int q1 = nphi - m;
-    for (int l = threadIdx.x; l < nth; l += 256) {
-        x0[l] = c[size_t(m) * nth + l];
-        x1[l] = two ? c[size_t(q1) * nth + l] : 0.0;
-    }
-    __syncthreads();
-    double y0, y1;
-    cols32(W + size_t(m) * nth * nth, x0, x1, o0, nth, sh + 2 * nth, y0, y1);
+    cols32(B + size_t(m) * nth * nth, x0, x1, o0, nth, sh + 2 * nth, y0, y1);
     const int j = o0 + int(threadIdx.x);
     if (threadIdx.x < 32 && j < nth) {
-        const double w = 1.0 / dmu[j];
-        ob[size_t(m) * nth + j] = y0 * w;
-        if (two) ob[size_t(q1) * nth + j] = y1 * w;
+        ob[size_t(m) * nth + j] = y0;
+        if (two) ob[size_t(q1) * nth + j] = y1;
     }
 }
 
-// Both steps on `stream`; c is a scratch vector set of N_phi N_theta doubles.
-inline void launch_outer(const double* g, size_t gq, double* c, double* ob, const double* W, const double* H,
-                         const double* beta, const double* dmu, int nth, int nphi, hipStream_t s)
+// The shell term of every component on `stream`: g (strided by gq) -> ob
+// ([q][N_theta], a different buffer: workgroups of one mode all read g_q).
+inline void launch_outer(const double* g, size_t gq, double* ob, const double* B, int nth, int nphi, hipStream_t s)
 {
     const dim3 grid(nphi / 2 + 1, (nth + 31) / 32);
     const size_t lds = (2 * size_t(nth) + 512) * sizeof(double);
-    hipLaunchKernelGGL(k_outer_coef, grid, dim3(256), lds, s, g, gq, c, H, beta, dmu, nth, nphi);
-    hipLaunchKernelGGL(k_outer_apply, grid, dim3(256), lds, s, c, ob, W, dmu, nth, nphi);
+    hipLaunchKernelGGL(k_shell_apply, grid, dim3(256), lds, s, g, gq, ob, B, nth, nphi);
 }
 
 // LDS bound of launch_outer: (2 N_theta + 512) doubles within 64 KB.

@@ -43,6 +43,8 @@ struct spp_plan_layout {
     size_t Sj = 0;      // S_j, [N_theta]
     size_t lamphi = 0;  // lambda_{phi,m}, [M]
     size_t mom = 0;     // factors of the momentum source's face integrals (spp_mom_layout)
+    size_t Bo = 0;      // outer-shell operator per mode, [M][N_theta(j')][N_theta(j)] (transposed)
+    size_t Bi = 0;      // inner-shell operator (regular inner condition), same layout; empty otherwise
     size_t total = 0;
 };
 
@@ -58,6 +60,7 @@ struct spp_plan_s {
     bool parity = false;                       // equator-symmetric theta grid: modes ordered even, odd
     int par_rn = 0;                            // tile width of the parity-split kernel (0: not used)
     std::vector<double> Fimg, Iimg, Rimg;      // images of the fused per-mode kernel
+    std::vector<double> Bo, Bi;                // shell operators H diag(beta) H^T D (gamma for Bi)
     bool fused_ok = false;                     // the fused per-mode path can run this grid
     std::atomic<int> path{SPP_PATH_AUTO};      // requested path (spp_plan_set_path)
     spp_plan_layout lay;

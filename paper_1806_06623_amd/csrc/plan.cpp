@@ -385,6 +385,43 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
             return spp_fail(SPP_EDEVICE, "spp_plan_create: theta eigen iteration did not converge");
         }
 
+        // shell operators of the boundary terms (Sec. 3.2): per mode m the
+        // outer-face term of a shell's Fourier component g is
+        // H diag(beta) H^T D g, and with the regular inner condition the
+        // inner-face term is the same with gamma.  Each is one N_theta x
+        // N_theta matrix B = H diag(c) W with W = H^T D, stored transposed
+        // (row j' holds B[.][j']) for the column kernel that applies it.
+        {
+            const size_t nn = size_t(nth) * nth;
+            p->Bo.assign(size_t(nm) * nn, 0.0);
+            if (p->inner_regular) p->Bi.assign(size_t(nm) * nn, 0.0);
+            auto shell_ops = [&](int m0, int stride) {
+                std::vector<double> Ht(nn);   // H^T, so that the inner loop runs along rows
+                for (int m = m0; m < nm; m += stride) {
+                    const double* Wm = &p->W[size_t(m) * nn];
+                    for (int j = 0; j < nth; ++j)
+                        for (int l = 0; l < nth; ++l) Ht[size_t(l) * nth + j] = p->H[size_t(m) * nn + size_t(j) * nth + l];
+                    for (int pass = 0; pass < (p->inner_regular ? 2 : 1); ++pass) {
+                        const double* c = &(pass == 0 ? p->beta : p->gamma)[size_t(m) * nth];
+                        double* B = &(pass == 0 ? p->Bo : p->Bi)[size_t(m) * nn];
+                        // B^T[j'][j] = sum_l W[l][j'] c_l H[j][l]
+                        for (int jp = 0; jp < nth; ++jp) {
+                            double* row = B + size_t(jp) * nth;
+                            for (int l = 0; l < nth; ++l) {
+                                const double t = Wm[size_t(l) * nth + jp] * c[l];
+                                const double* hl = &Ht[size_t(l) * nth];
+                                for (int j = 0; j < nth; ++j) row[j] += t * hl[j];
+                            }
+                        }
+                    }
+                }
+            };
+            std::vector<std::thread> ops;
+            for (int t = 1; t < nthreads; ++t) ops.emplace_back(shell_ops, t, nthreads);
+            shell_ops(0, nthreads);
+            for (auto& th : ops) th.join();
+        }
+
         // theta and phi tables of the spectral residual (mixed-precision refinement)
         p->sig = G.sigma;
         p->dmu = G.dmu;
@@ -540,6 +577,8 @@ extern "C" spp_status spp_plan_create(spp_grid g, spp_plan* out)
         L.Sj = take(p->Sj.size());
         L.lamphi = take(p->lamphi.size());
         L.mom = take(p->mom.size());
+        L.Bo = take(p->Bo.size());
+        L.Bi = take(p->Bi.size());
         L.total = off;
         // the larger of what either path needs (spp_plan_set_path may switch
         // paths after the caller has sized its workspace)
@@ -642,6 +681,8 @@ extern "C" spp_status spp_plan_upload(spp_plan p, void* plan_dev, void* stream)
     put(p->lay.sig, p->sig);
     put(p->lay.dmu, p->dmu);
     put(p->lay.Sj, p->Sj);
+    put(p->lay.Bo, p->Bo);
+    put(p->lay.Bi, p->Bi);
     put(p->lay.lamphi, p->lamphi);
     put(p->lay.mom, p->mom);
     hipStream_t s = static_cast<hipStream_t>(stream);

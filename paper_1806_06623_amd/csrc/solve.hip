@@ -1198,17 +1198,14 @@ struct MixedLayout {
 
 // The outer-face term beta(A) g_N (and with the regular inner condition the
 // inner-face term gamma(A) g_1) of every Fourier component of the field F
-// [q][i][j] into ob (ib) [q][j]; c is a scratch of N_phi N_theta doubles.
-void launch_shell_terms(const spp_plan_s* p, const double* F, double* c, double* ob, double* ib, hipStream_t s)
+// [q][i][j] into ob (ib) [q][j].
+void launch_shell_terms(const spp_plan_s* p, const double* F, double* ob, double* ib, hipStream_t s)
 {
     const PlanTables T(p);
     const auto& L = p->lay;
     const int nr = p->nr, nth = p->nth, nphi = p->nphi;
-    faceflux::launch_outer(F + size_t(nr - 1) * nth, size_t(nr) * nth, c, ob, T.d(L.W), T.d(L.H), T.d(L.beta),
-                           T.d(L.dmu), nth, nphi, s);
-    if (ib)
-        faceflux::launch_outer(F, size_t(nr) * nth, c, ib, T.d(L.W), T.d(L.H), T.d(L.gamma), T.d(L.dmu), nth,
-                               nphi, s);
+    faceflux::launch_outer(F + size_t(nr - 1) * nth, size_t(nr) * nth, ob, T.d(L.Bo), nth, nphi, s);
+    if (ib) faceflux::launch_outer(F, size_t(nr) * nth, ib, T.d(L.Bi), nth, nphi, s);
 }
 
 }  // namespace
@@ -1264,8 +1261,8 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
     for (int it = 0; it <= n_refine; ++it) {
         const double* src = St;
         if (it > 0) {
-            // boundary terms of the current g; Z is free until the projection below
-            launch_shell_terms(p, Gf, Z, ob, ib, s);
+            // boundary terms of the current g
+            launch_shell_terms(p, Gf, ob, ib, s);
             hipLaunchKernelGGL(k_residual, dim3(rgx, nphi), dim3(256), 0, s, St, Gf, ob, ib, Y, rt, nr, nth, nphi,
                                part + size_t(it) * nphi, it == 1 ? part : nullptr);
             src = Y;
@@ -1292,10 +1289,10 @@ spp_status spp_launch_solve_mixed(const spp_plan_s* p, spp_precision, int n_refi
 // Face fluxes of grad Phi (fluxes.hip.h).  The outer face needs the boundary
 // term of Sec. 3.2 on the outermost shell, T = beta(A) Phi_shell, which acts
 // per angular eigenmode: the shell's Fourier components (forward FFT of its
-// N_theta lines), the two per-mode products of faceflux::launch_outer, and
+// N_theta lines), the per-mode product of faceflux::launch_outer, and
 // the inverse FFT back to [j][k].  Workspace after its status record: two
-// shell-sized buffers A, B (A: spectrum, B: coefficients, A: boundary term per
-// component, B: T).
+// shell-sized buffers A, B (A: spectrum, B: boundary term per component, A:
+// T).
 spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double* fr, double* ft, double* fp,
                                   void* ws, void* stream)
 {
@@ -1316,12 +1313,12 @@ spp_status spp_launch_face_fluxes(const spp_plan_s* p, const double* phi, double
                                      "stored (grids with r_{1/2} > 0 need the zero-flux condition here)");
     if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, A, tw, 1.0 / nphi, nth, s))
         return spp_fail(SPP_ENOTSUP, "spp_face_fluxes: unsupported nphi");
-    faceflux::launch_outer(A, size_t(nth), B, A, T.d(L.W), T.d(L.H), T.d(L.beta), T.d(L.dmu), nth, nphi, s);
-    launch_fft(nphi, false, A, B, tw, 1.0, nth, s);
+    faceflux::launch_outer(A, size_t(nth), B, T.d(L.Bo), nth, nphi, s);
+    launch_fft(nphi, false, B, A, tw, 1.0, nth, s);
     const faceflux::Tables t{T.d(L.alpha), T.d(L.VR), T.d(L.sig), T.d(L.dmu), T.d(L.Sj)};
     const int gx = (plane + faceflux::THREADS - 1) / faceflux::THREADS;
     const int chunks = (nr + faceflux::ROWS - 1) / faceflux::ROWS;
-    hipLaunchKernelGGL(faceflux::k_face_fluxes, dim3(gx * chunks), dim3(faceflux::THREADS), 0, s, phi, B, fr, ft, fp,
+    hipLaunchKernelGGL(faceflux::k_face_fluxes, dim3(gx * chunks), dim3(faceflux::THREADS), 0, s, phi, A, fr, ft, fp,
                        t, nr, nth, nphi, 2.0 * M_PI / nphi, gx);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return spp_fail(SPP_EDEVICE, std::string("spp_face_fluxes: ") + hipGetErrorString(e));
@@ -1350,8 +1347,8 @@ spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G,
         return spp_fail(SPP_ENOTSUP, "spp_momentum_source: grids with the regular inner condition are not supported");
     if (!launch_fft(nphi, true, phi + size_t(nr - 1) * plane, A, tw, 1.0 / nphi, nth, s))
         return spp_fail(SPP_ENOTSUP, "spp_momentum_source: unsupported nphi");
-    faceflux::launch_outer(A, size_t(nth), B, A, T.d(L.W), T.d(L.H), T.d(L.beta), T.d(L.dmu), nth, nphi, s);
-    launch_fft(nphi, false, A, B, tw, 1.0, nth, s);
+    faceflux::launch_outer(A, size_t(nth), B, T.d(L.Bo), nth, nphi, s);
+    launch_fft(nphi, false, B, A, tw, 1.0, nth, s);
     const spp_mom_layout M(nr, nth, nphi);
     const double* q = T.d(L.mom);
     const momentum::Tables t{q + M.R2, q + M.ring, q + M.invr, q + M.invdr, q + M.is2, q + M.isc, q + M.is,
@@ -1369,11 +1366,11 @@ spp_status spp_launch_momentum(const spp_plan_s* p, const double* phi, double G,
         // whole workgroups only (every thread on a cell) unless the plane ends mid-workgroup
         auto kern = (nth * nphi) % momentum::THREADS == 0 ? momentum::k_momentum_rows<false>
                                                           : momentum::k_momentum_rows<true>;
-        hipLaunchKernelGGL(kern, dim3(gx * lchunks), dim3(momentum::THREADS), 0, s, phi, B, fx,
+        hipLaunchKernelGGL(kern, dim3(gx * lchunks), dim3(momentum::THREADS), 0, s, phi, A, fx,
                            fy, fz, t, nr, nth, nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
     } else {
         auto kern = nphi % 64 == 0 ? momentum::k_momentum<true> : momentum::k_momentum<false>;
-        hipLaunchKernelGGL(kern, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, B, fx, fy, fz, t, nr, nth,
+        hipLaunchKernelGGL(kern, dim3(gx * chunks), dim3(momentum::THREADS), 0, s, phi, A, fx, fy, fz, t, nr, nth,
                            nphi, 2.0 * M_PI / nphi, 1.0 / (4.0 * M_PI * G), 1.0 / (ro * ro), gx);
     }
     const hipError_t e = hipGetLastError();
@@ -1400,24 +1397,25 @@ spp_status spp_launch_residual(const spp_plan_s* p, const double* rho, const dou
     double *C = reinterpret_cast<double*>(w + 2 * sh), *D = reinterpret_cast<double*>(w + 3 * sh);
     if (nth > faceflux::OUTER_NTH_MAX)
         return spp_fail(SPP_ENOTSUP, "spp_residual: needs N_theta <= " + std::to_string(faceflux::OUTER_NTH_MAX));
-    auto shell_term = [&](const double* shell, const double* coef, double* spec, double* out) {
+    // shell -> spec (Fourier components) -> tmp (boundary term per component) -> spec ([j][k])
+    auto shell_term = [&](const double* shell, const double* op, double* spec, double* tmp) {
         launch_fft(nphi, true, shell, spec, tw, 1.0 / nphi, nth, s);
-        faceflux::launch_outer(spec, size_t(nth), out, spec, T.d(L.W), T.d(L.H), coef, T.d(L.dmu), nth, nphi, s);
-        launch_fft(nphi, false, spec, out, tw, 1.0, nth, s);
+        faceflux::launch_outer(spec, size_t(nth), tmp, op, nth, nphi, s);
+        launch_fft(nphi, false, tmp, spec, tw, 1.0, nth, s);
     };
-    shell_term(phi + size_t(nr - 1) * plane, T.d(L.beta), A, B);
-    if (p->inner_regular) shell_term(phi, T.d(L.gamma), C, D);
+    shell_term(phi + size_t(nr - 1) * plane, T.d(L.Bo), A, B);
+    if (p->inner_regular) shell_term(phi, T.d(L.Bi), C, D);
     const ResidualTables rt{T.d(L.alpha), T.d(L.V), T.d(L.VR), T.d(L.sig), T.d(L.dmu), T.d(L.Sj), T.d(L.lamphi)};
     const int gx = (plane + 255) / 256;
     const double dphi = 2.0 * M_PI / nphi;
-    const double* tin = p->inner_regular ? D : nullptr;
+    const double* tin = p->inner_regular ? C : nullptr;
     if (256 % nphi == 0) {
         const int chunks = (nr + RES_LDS_ROWS - 1) / RES_LDS_ROWS;
-        hipLaunchKernelGGL(k_residual_rows<RES_LDS_ROWS>, dim3(gx * chunks), dim3(256), 0, s, rho, phi, B, tin, r, rt,
+        hipLaunchKernelGGL(k_residual_rows<RES_LDS_ROWS>, dim3(gx * chunks), dim3(256), 0, s, rho, phi, A, tin, r, rt,
                            4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
     } else {
         const int chunks = (nr + RROWS - 1) / RROWS;
-        hipLaunchKernelGGL(k_residual_phys, dim3(gx * chunks), dim3(256), 0, s, rho, phi, B, tin, r, rt,
+        hipLaunchKernelGGL(k_residual_phys, dim3(gx * chunks), dim3(256), 0, s, rho, phi, A, tin, r, rt,
                            4.0 * M_PI * G, nr, nth, nphi, 1.0 / (dphi * dphi), gx);
     }
     const hipError_t e = hipGetLastError();
