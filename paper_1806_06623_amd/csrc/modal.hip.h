@@ -172,6 +172,23 @@ __device__ __forceinline__ void image_dma(double* __restrict__ Bs, const double*
     }
 }
 
+// The same for an image of any even length: the last piece moves only the
+// lanes whose 16 bytes lie inside the image.
+template <int ELEMS, int NWAVES>
+__device__ __forceinline__ void image_dma_tail(double* __restrict__ Bs, const double* __restrict__ img, int wq,
+                                               int lane)
+{
+    constexpr int PIECES = (ELEMS + 127) / 128;
+    static_assert(ELEMS % 2 == 0, "image in whole 16-byte pairs");
+#pragma unroll
+    for (int u = 0; u < (PIECES + NWAVES - 1) / NWAVES; ++u) {
+        const int pc = wq + NWAVES * u;                 // wave-uniform
+        if (pc < PIECES && pc * 128 + 2 * lane < ELEMS)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(img + pc * 128 + 2 * lane),
+                                             (__attribute__((address_space(3))) void*)(Bs + pc * 128), 16, 0, 0);
+    }
+}
+
 // Calls f(integral_constant<int, I>) for I = I0 .. N-1 in order.
 template <int I0, int N, class F>
 __device__ __forceinline__ void static_for(F&& f)
@@ -352,19 +369,32 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         t_lam[l] = lam[size_t(m) * nth + L];
         t_bo[l] = beta[size_t(m) * nth + L];
     }
-    // the radial row records (built by the plan, the same for every unit)
-    stage_image<(ROWS + P) * modalimg::RECD>(t_rec, Rimg, tid0);
+    // the radial row records (built by the plan, the same for every unit).
+    // With two column blocks they and the second half of the image are copied
+    // into LDS by direct loads from quartet 2, issued here, so that no wave
+    // holds them in registers through the first products (the compiler would
+    // instead reload such values one after another at their stores, each load
+    // waiting for every load in flight).  The barrier's release makes quartet
+    // 2 wait for its copies (they are LDS writes); they overlap the other
+    // waves' loads.
+    constexpr int RECE = (ROWS + P) * modalimg::RECD;
+    if constexpr (SPLIT) {
+        if (w >> 2 == 2) {
+            image_dma<HALF_E, 4>(Bs + HALF_E, fimg + HALF_E, w - 8, lane);
+            image_dma_tail<RECE, 4>(t_rec, Rimg, w - 8, lane);
+        }
+    } else {
+        stage_image<RECE>(t_rec, Rimg, tid0);
+    }
     __syncthreads();
+    if constexpr (SPLIT) {
+        if (w >> 2 == 2) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the copies have landed
+    }
     if constexpr (NCH > 1) load_a(bb, arow(1 % T), 1 / T, g, h);
-    ImagePart<HALF_E> second;
-    if constexpr (SPLIT) load_part<HALF_E, HALF_E>(second, fimg, tid0);
 
     static_for<0, NCH>([&](auto cc) __attribute__((always_inline)) {
         constexpr int c = decltype(cc)::value, rb = c % T, kc = c / T;
-        if constexpr (SPLIT && c == T) {
-            store_part<HALF_E, HALF_E>(Bs, second, tid0);
-            __syncthreads();
-        }
+        if constexpr (SPLIT && c == T) __syncthreads();
 
         // issue priority falls as a wave gets ahead, so that the three waves of
         // a SIMD share the matrix pipe evenly and finish the product together
