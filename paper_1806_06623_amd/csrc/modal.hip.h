@@ -595,42 +595,42 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         D(0) = xL;
         D(1) -= (pt.x * pt.z) * xL;
         D(CH - 1) -= (pt.y * pt.z) * xR;
-        double invw[CH];
+        // forward elimination (Thomas): pivot w_k = d_k - a_{k-1}^2 / w_{k-1};
+        // D(k) becomes y_k = (D_k - a_{k-1} y_{k-1}) / w_k and cw[k] keeps
+        // c_k = a_k / w_k, so that the back substitution x_k = y_k - c_k x_{k+1}
+        // needs no record loads
+        double cw[CH];
         NEXT_BASE(xL);
         double4 cur = ROW(1);
         double4 nx = ROW(2);
         double a2p = A2(1), a2n = A2(2);
-        invw[1] = radial::recip(DIAG(cur));
+        double iw = radial::recip(DIAG(cur));
+        D(1) *= iw;
+        cw[1] = cur.w * iw;
         double al_prev = cur.w;
 #pragma unroll
         for (int k = 2; k < CH; ++k) {
             cur = nx;
             double a2c = a2n;
-            TIE(cur, invw[k - 1]);
-            TIE1(a2c, invw[k - 1]);
-            NEXT_BASE(invw[k - 1]);
+            TIE(cur, iw);
+            TIE1(a2c, iw);
+            NEXT_BASE(iw);
             if (k + 1 < CH) {
                 nx = ROW(k + 1);
                 a2n = A2(k + 1);
             }
-            const double mult = al_prev * invw[k - 1];
-            invw[k] = radial::recip(DIAG(cur) - a2p * invw[k - 1]);
-            D(k) -= mult * D(k - 1);
+            iw = radial::recip(DIAG(cur) - a2p * iw);
+            D(k) = (D(k) - al_prev * D(k - 1)) * iw;
+            if (k + 1 < CH) cw[k] = cur.w * iw;
             al_prev = cur.w;
             a2p = a2c;
         }
-        // back substitution; alpha of row k is read one row ahead
-        double xn = D(CH - 1) * invw[CH - 1];
-        D(CH - 1) = xn;
-        NEXT_BASE(xn);
-        double an = ROW(CH - 2).w;
+        // back substitution from x_{CH-1} = y_{CH-1}
+        double xn = D(CH - 1);
 #pragma unroll
         for (int k = CH - 2; k >= 1; --k) {
-            double ak = an;
-            asm volatile("" : "+v"(ak) : "v"(xn));
-            NEXT_BASE(xn);
-            if (k > 1) an = ROW(k - 1).w;
-            xn = (D(k) - ak * xn) * invw[k];
+            xn = D(k) - cw[k] * xn;
+            asm volatile("" : "+v"(xn));   // keeps the sweep ahead of the next pass's code
             D(k) = xn;
         }
     };
