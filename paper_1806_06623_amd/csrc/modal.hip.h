@@ -447,6 +447,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
 #define DIAG(r) ((r).x + (r).y * lm - (r).z * bo)
 #define TIE(r, dep) asm volatile("" : "+v"((r).x), "+v"((r).y), "+v"((r).z), "+v"((r).w) : "v"(dep))
 #define NEXT_BASE(dep) asm volatile("" : "+v"(rb0) : "v"(dep))
+#define NEXT_BASE2(d1, d2) asm volatile("" : "+v"(rb0) : "v"(d1), "v"(d2))
 
     // pass 1 of column group cb.  The interior rows 1..n (n = CH - 1) of the
     // chunk form a tridiagonal block A (scaled by 2^-e_p) coupled to the
@@ -472,62 +473,48 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         unsigned rb0 = unsigned(sk) * RB;
 #pragma unroll
         for (int k = 0; k < CH; ++k) D(k) *= VOL(k);
-        // forward: pk = p_{k-1}, pk1 = p_{k-2}, al and a2 the coupling of row k-1
-        double4 cur = ROW(1);
-        double4 nx = ROW(2);
-        double a2 = A2(1), a2n = A2(2);
-        double pk = DIAG(cur), pk1 = 1.0, S = D(1), al = cur.w;
+        // the forward sweep (p, S) from row 1 up and the backward sweep (q, T)
+        // from row n down are independent: they run interleaved, one row of
+        // each per step, whose record loads are issued together after the
+        // previous step's pivots and awaited once.
+        // Forward: pk = p_{k-1}, pk1 = p_{k-2}, al and a2 the coupling of row
+        // k-1; backward: qk = q_{k+1}, qk1 = q_{k+2}
+        double a2, pk, pk1 = 1.0, S = D(1), al;
+        double qk, qk1 = 1.0, Tk = D(CH - 1);
+        {
+            const double4 cf = ROW(1), cr = ROW(CH - 1);
+            a2 = A2(1);
+            pk = DIAG(cf);
+            al = cf.w;
+            qk = DIAG(cr);
+        }
 #pragma unroll
-        for (int k = 2; k < CH; ++k) {
-            cur = nx;
-            double a2c = a2n;
-            TIE(cur, pk);
-            TIE1(a2c, pk);
-            NEXT_BASE(pk);
-            if (k + 1 < CH) {
-                nx = ROW(k + 1);
-                a2n = A2(k + 1);
-            }
-            S = pk * D(k) - al * S;
-            const double pn = DIAG(cur) * pk - a2 * pk1;
+        for (int i = 0; i < CH - 2; ++i) {
+            const int kf = 2 + i, kr = CH - 2 - i;
+            NEXT_BASE2(pk, qk);
+            const double4 cf = ROW(kf), cr = ROW(kr);
+            const double a2cf = A2(kf), a2cr = A2(kr);
+            S = pk * D(kf) - al * S;
+            const double pn = DIAG(cf) * pk - a2 * pk1;
             pk1 = pk;
             pk = pn;
-            al = cur.w;
-            a2 = a2c;
+            al = cf.w;
+            a2 = a2cf;
+            Tk = qk * D(kr) - cr.w * Tk;
+            const double qn = DIAG(cr) * qk - a2cr * qk1;
+            qk1 = qk;
+            qk = qn;
         }
         const double ipn = radial::recip(pk);
-        NEXT_BASE(ipn);
+        const double iq1 = radial::recip(qk);
+        NEXT_BASE2(ipn, iq1);
         const double4 pt = ROW(CH);             // oL, oR, 2^-e_p, -oL oR 2^-e_p prod a
         nxt[(0 * P + p) * FP + lr] = pt.w * ipn;
         nxt[(1 * P + p) * FP + lr] = -(pt.y * pt.y * pt.z) * pk1 * ipn;
         nxt[(2 * P + p) * FP + lr] = pt.y * S * ipn;
-        // backward: qk = q_{k+1}, qk1 = q_{k+2}
-        cur = ROW(CH - 1);
-        nx = ROW(CH - 2);
-        a2n = A2(CH - 2);
-        double qk = DIAG(cur), qk1 = 1.0, Tk = D(CH - 1);
-#pragma unroll
-        for (int k = CH - 2; k >= 1; --k) {
-            cur = nx;
-            double a2c = a2n;
-            TIE(cur, qk);
-            TIE1(a2c, qk);
-            NEXT_BASE(qk);
-            if (k > 1) {
-                nx = ROW(k - 1);
-                a2n = A2(k - 1);
-            }
-            Tk = qk * D(k) - cur.w * Tk;
-            const double qn = DIAG(cur) * qk - a2c * qk1;
-            qk1 = qk;
-            qk = qn;
-        }
-        const double iq1 = radial::recip(qk);
-        NEXT_BASE(iq1);
-        const double4 ps = ROW(CH);             // the partition slot again (not kept live)
-        own[(0 * P + p) * FP + lr] = DIAG(ROW(0)) - (ps.x * ps.x * ps.z) * qk1 * iq1;
-        own[(1 * P + p) * FP + lr] = ps.w * iq1;
-        own[(2 * P + p) * FP + lr] = D(0) - ps.x * Tk * iq1;
+        own[(0 * P + p) * FP + lr] = DIAG(ROW(0)) - (pt.x * pt.x * pt.z) * qk1 * iq1;
+        own[(1 * P + p) * FP + lr] = pt.w * iq1;
+        own[(2 * P + p) * FP + lr] = D(0) - pt.x * Tk * iq1;
     };
 
     // The separator rows of a column form a tridiagonal system of P = 48
@@ -670,6 +657,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
 #undef DIAG
 #undef TIE
 #undef NEXT_BASE
+#undef NEXT_BASE2
 #undef D
 
     // ---- inverse projection, tile by tile through a per-wave transpose
