@@ -441,9 +441,10 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     // immediate offset from the same register
 #define REC_AT(off) (reinterpret_cast<const char*>(t_rec) + (off))
 #define ROW(k) (*reinterpret_cast<const double4*>(REC_AT(rb0 + (k) * RB)))
-#define A2(k) (*reinterpret_cast<const double*>(REC_AT(rb0 + (k) * RB + 32)))
+// a^2 of a row: the record holds it as the square of its a, which is computed
+// instead of loaded
+#define SQ(a) ((a) * (a))
 #define VOL(k) (*reinterpret_cast<const double*>(REC_AT(rb0 + (k) * RB + 40)))
-#define TIE1(v, dep) asm volatile("" : "+v"(v) : "v"(dep))
 #define DIAG(r) ((r).x + (r).y * lm - (r).z * bo)
 #define TIE(r, dep) asm volatile("" : "+v"((r).x), "+v"((r).y), "+v"((r).z), "+v"((r).w) : "v"(dep))
 #define NEXT_BASE(dep) asm volatile("" : "+v"(rb0) : "v"(dep))
@@ -477,13 +478,12 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         // from row n down are independent: they run interleaved, one row of
         // each per step, whose record loads are issued together after the
         // previous step's pivots and awaited once.
-        // Forward: pk = p_{k-1}, pk1 = p_{k-2}, al and a2 the coupling of row
+        // Forward: pk = p_{k-1}, pk1 = p_{k-2}, al the coupling a of row
         // k-1; backward: qk = q_{k+1}, qk1 = q_{k+2}
-        double a2, pk, pk1 = 1.0, S = D(1), al;
+        double pk, pk1 = 1.0, S = D(1), al;
         double qk, qk1 = 1.0, Tk = D(CH - 1);
         {
             const double4 cf = ROW(1), cr = ROW(CH - 1);
-            a2 = A2(1);
             pk = DIAG(cf);
             al = cf.w;
             qk = DIAG(cr);
@@ -493,15 +493,13 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
             const int kf = 2 + i, kr = CH - 2 - i;
             NEXT_BASE2(pk, qk);
             const double4 cf = ROW(kf), cr = ROW(kr);
-            const double a2cf = A2(kf), a2cr = A2(kr);
             S = pk * D(kf) - al * S;
-            const double pn = DIAG(cf) * pk - a2 * pk1;
+            const double pn = DIAG(cf) * pk - SQ(al) * pk1;
             pk1 = pk;
             pk = pn;
             al = cf.w;
-            a2 = a2cf;
             Tk = qk * D(kr) - cr.w * Tk;
-            const double qn = DIAG(cr) * qk - a2cr * qk1;
+            const double qn = DIAG(cr) * qk - SQ(cr.w) * qk1;
             qk1 = qk;
             qk = qn;
         }
@@ -590,7 +588,6 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         NEXT_BASE(xL);
         double4 cur = ROW(1);
         double4 nx = ROW(2);
-        double a2p = A2(1), a2n = A2(2);
         double iw = radial::recip(DIAG(cur));
         D(1) *= iw;
         cw[1] = cur.w * iw;
@@ -598,19 +595,13 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
 #pragma unroll
         for (int k = 2; k < CH; ++k) {
             cur = nx;
-            double a2c = a2n;
             TIE(cur, iw);
-            TIE1(a2c, iw);
             NEXT_BASE(iw);
-            if (k + 1 < CH) {
-                nx = ROW(k + 1);
-                a2n = A2(k + 1);
-            }
-            iw = radial::recip(DIAG(cur) - a2p * iw);
+            if (k + 1 < CH) nx = ROW(k + 1);
+            iw = radial::recip(DIAG(cur) - SQ(al_prev) * iw);
             D(k) = (D(k) - al_prev * D(k - 1)) * iw;
             if (k + 1 < CH) cw[k] = cur.w * iw;
             al_prev = cur.w;
-            a2p = a2c;
         }
         // back substitution from x_{CH-1} = y_{CH-1}
         double xn = D(CH - 1);
@@ -651,9 +642,8 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
 #undef PART_INDICES
 #undef REC_AT
 #undef ROW
-#undef A2
+#undef SQ
 #undef VOL
-#undef TIE1
 #undef DIAG
 #undef TIE
 #undef NEXT_BASE
