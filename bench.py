@@ -80,14 +80,17 @@ def stage_model(nr, nth, nphi, parity, fused):
 TRAFFIC = {
     "modal::k_modal": {"grid": (550, 128, 256),
                        "sources": ("modal.hip.h", "modal_layout.h", "radial.hip.h", "status.h", "solve.hip"),
-                       "source_digest": "21caead8444a8669",
-                       "bytes_per_launch": (81373.2 * 2.0 + 140806.0) * 1024.0},
+                       "source_digest": "faa3430cfd457ae8",
+                       "bytes_per_launch": (81356.6 * 2.0 + 140806.0) * 1024.0},
     "faceflux::k_face_fluxes": {"grid": (550, 128, 256), "sources": ("fluxes.hip.h", "xcd.h", "solve.hip"),
-                                "source_digest": "275d2b8480a65ffe",
-                                "bytes_per_launch": (74474.1 * 2.0 + 422605.1) * 1024.0},
+                                "source_digest": "b2a25584f1ab1bc0",
+                                "bytes_per_launch": (74482.1 * 2.0 + 422617.4) * 1024.0},
     "momentum::k_momentum_rows": {"grid": (550, 128, 256), "sources": ("momentum.hip.h", "xcd.h", "solve.hip"),
-                                  "source_digest": "8bfea88ec10d9dfb",
-                                  "bytes_per_launch": (78510.8 * 2.0 + 422400.2) * 1024.0},
+                                  "source_digest": "14a8e28ce87a9ca8",
+                                  "bytes_per_launch": (78511.6 * 2.0 + 422400.1) * 1024.0},
+    "k_residual_rows": {"grid": (550, 128, 256), "sources": ("solve.hip", "internal.h", "xcd.h", "status.h"),
+                        "source_digest": "3175b7ca1d3e8f72",
+                        "bytes_per_launch": (148724.0 * 2.0 + 140800.0) * 1024.0},
 }
 
 
@@ -466,7 +469,8 @@ def main():
         resid = {"ms": round(ms, 5), "alg_bytes": rbytes, "GBps": round(rbytes / (ms * 1e-3) / 1e9, 1),
                  "hbm_frac": round(rbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "note": "whole entry point: outer-shell boundary term (shell FFT, per-mode beta, inverse FFT) "
-                         "and the flux stencil; algorithmic bytes = rho and Phi read once + r written"}
+                         "and the flux stencil; algorithmic bytes = rho and Phi read once + r written",
+                 "kernel_traffic": measured_traffic("k_residual_rows", nr, nth, nphi)}
         log(f"residual: {ms * 1e3:.1f} us per call, {resid['GBps']} GB/s")
         del R
 
