@@ -260,6 +260,17 @@ __device__ __forceinline__ double row_move(double v, double old)
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// The same with zero for lanes without a source in their row (the DPP bound
+// control writes the zero; no fill value is moved into the destination first).
+template <int CTRL>
+__device__ __forceinline__ double row_move0(double v)
+{
+    const long long vb = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(int(vb), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(int(vb >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // One level of parallel cyclic reduction over the 16 lanes of a row, stride
 // HS: row t (a x_{t-1} + b x_t + c x_{t+1} = d in the current stride) is
 // combined with rows t - HS and t + HS; a partner outside the row contributes
@@ -268,10 +279,10 @@ __device__ __forceinline__ double row_move(double v, double old)
 template <int HS>
 __device__ __forceinline__ void pcr16_level(double& ra, double& rb, double& rc, double& rd, int t)
 {
-    const double am = row_move<0x110 + HS>(ra, 0.0), bm = row_move<0x110 + HS>(rb, 1.0);
-    const double cm = row_move<0x110 + HS>(rc, 0.0), dm = row_move<0x110 + HS>(rd, 0.0);
-    const double ap = row_move<0x100 + HS>(ra, 0.0), bp = row_move<0x100 + HS>(rb, 1.0);
-    const double cp = row_move<0x100 + HS>(rc, 0.0), dp = row_move<0x100 + HS>(rd, 0.0);
+    const double am = row_move0<0x110 + HS>(ra), bm = row_move<0x110 + HS>(rb, 1.0);
+    const double cm = row_move0<0x110 + HS>(rc), dm = row_move0<0x110 + HS>(rd);
+    const double ap = row_move0<0x100 + HS>(ra), bp = row_move<0x100 + HS>(rb, 1.0);
+    const double cp = row_move0<0x100 + HS>(rc), dp = row_move0<0x100 + HS>(rd);
     const double a = t >= HS ? -ra * radial::recip(bm) : 0.0;
     const double c = t + HS < 16 ? -rc * radial::recip(bp) : 0.0;
     rb = rb + a * cm + c * ap;
@@ -547,8 +558,8 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         const double e2 = (qb[1] * qd[2] - qa[2] * qd[1]) * idet, f2 = qa[2] * qa[1] * idet, g2 = -qb[1] * qc[2] * idet;
         // the previous lane's x_{3t-1} = e2' + f2' x_{3t-3} + g2' x_{3t} enters row 3t
         // (lane 0 has qa[0] = 0)
-        const double e2p = row_move<0x111>(e2, 0.0), f2p = row_move<0x111>(f2, 0.0);
-        const double g2p = row_move<0x111>(g2, 0.0);
+        const double e2p = row_move0<0x111>(e2), f2p = row_move0<0x111>(f2);
+        const double g2p = row_move0<0x111>(g2);
         double ra = qa[0] * f2p;
         double rb = qb[0] + qa[0] * g2p + qc[0] * f1;
         double rc = qc[0] * g1;
@@ -558,7 +569,7 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
         pcr16_level<4>(ra, rb, rc, rd, t);
         pcr16_level<8>(ra, rb, rc, rd, t);
         const double x0 = rd * radial::recip(rb);
-        const double x3 = row_move<0x101>(x0, 0.0);    // x_{3t+3}; lane 15 has g1 = g2 = 0
+        const double x3 = row_move0<0x101>(x0);        // x_{3t+3}; lane 15 has g1 = g2 = 0
         xsb[(3 * t + 0) * FP + c] = x0;
         xsb[(3 * t + 1) * FP + c] = e1 + f1 * x0 + g1 * x3;
         xsb[(3 * t + 2) * FP + c] = e2 + f2 * x0 + g2 * x3;
