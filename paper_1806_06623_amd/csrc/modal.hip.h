@@ -250,18 +250,8 @@ __device__ __forceinline__ void set_priority()
 
 // Move a double between lanes of a 16-lane row (DPP row shift): with
 // CTRL = 0x110 + n (row_shr) lane i receives lane i - n, with 0x100 + n
-// (row_shl) lane i + n; lanes without a source in their row receive `old`.
-template <int CTRL>
-__device__ __forceinline__ double row_move(double v, double old)
-{
-    const long long vb = __double_as_longlong(v), ob = __double_as_longlong(old);
-    const int lo = __builtin_amdgcn_update_dpp(int(ob), int(vb), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(int(ob >> 32), int(vb >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-// The same with zero for lanes without a source in their row (the DPP bound
-// control writes the zero; no fill value is moved into the destination first).
+// (row_shl) lane i + n; lanes without a source in their row receive zero
+// (written by the DPP bound control, with no fill value moved first).
 template <int CTRL>
 __device__ __forceinline__ double row_move0(double v)
 {
@@ -279,9 +269,11 @@ __device__ __forceinline__ double row_move0(double v)
 template <int HS>
 __device__ __forceinline__ void pcr16_level(double& ra, double& rb, double& rc, double& rd, int t)
 {
-    const double am = row_move0<0x110 + HS>(ra), bm = row_move<0x110 + HS>(rb, 1.0);
+    // bm and bp of a missing partner are zero; the selects below discard the
+    // reciprocals formed from them
+    const double am = row_move0<0x110 + HS>(ra), bm = row_move0<0x110 + HS>(rb);
     const double cm = row_move0<0x110 + HS>(rc), dm = row_move0<0x110 + HS>(rd);
-    const double ap = row_move0<0x100 + HS>(ra), bp = row_move<0x100 + HS>(rb, 1.0);
+    const double ap = row_move0<0x100 + HS>(ra), bp = row_move0<0x100 + HS>(rb);
     const double cp = row_move0<0x100 + HS>(rc), dp = row_move0<0x100 + HS>(rd);
     const double a = t >= HS ? -ra * radial::recip(bm) : 0.0;
     const double c = t + HS < 16 ? -rc * radial::recip(bp) : 0.0;
