@@ -68,6 +68,10 @@ def _both_paths(r_if, th_if, nphi, rho):
     (7, 12, 256, 19),     # register-pass folded FFTs: 42 pairs, blocks span rows, ragged last block
     (9, 100, 256, 20),    # 450 pairs, h = 50
     (64, 16, 256, 21),    # 32 blocks of 16 pairs: the XCD-ordered block range of the inverse
+    (300, 24, 16, 22),    # one column tile, two row tiles per wave (8-row chunks)
+    (500, 32, 8, 23),     # one column tile, three row tiles
+    (100, 48, 16, 24),    # two column tiles, one row tile (4-row chunks)
+    (450, 60, 8, 25),     # two column tiles, three row tiles, h = 30 (padded columns)
 ])
 def test_fused_matches_oracle_and_staged(nr, nth, nphi, seed):
     print(f"[case] fused {nr}x{nth}x{nphi} seed {seed}", flush=True)
