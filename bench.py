@@ -80,7 +80,7 @@ def stage_model(nr, nth, nphi, parity, fused):
 TRAFFIC = {
     "modal::k_modal": {"grid": (550, 128, 256),
                        "sources": ("modal.hip.h", "modal_layout.h", "radial.hip.h", "status.h", "solve.hip"),
-                       "source_digest": "291911bc44ebee51",
+                       "source_digest": "9387555aa5f1cb12",
                        "bytes_per_launch": (81339.5 * 2.0 + 140806.0) * 1024.0},
     "faceflux::k_face_fluxes": {"grid": (550, 128, 256), "sources": ("fluxes.hip.h", "xcd.h", "solve.hip"),
                                 "source_digest": "b2a25584f1ab1bc0",

@@ -435,11 +435,12 @@ __global__ __launch_bounds__(THREADS) void k_modal(double* __restrict__ X, const
     const int s0 = p * CH, sk = s0 + p;                                 \
     (void)s0; (void)sk
 
-    // Row records are read one row ahead: the empty asm statements take the
-    // previous row's pivot as input, which pins the load of row k+1 after the
-    // pivot of row k-1 and the first use of row k after the pivot of row k-1,
-    // so the load latency overlaps one row of the recurrence and the records
-    // of the other rows are never live at the same time.
+    // Row records are loaded behind empty asm statements that take pivots as
+    // inputs, so that the records of other rows are never live at the same
+    // time: pass 2 reads one row ahead (the load of row k+1 and the first use
+    // of row k are pinned after the pivot of row k-1, so the load latency
+    // overlaps one row of the recurrence); pass 1 loads the two rows of a step
+    // after both previous pivots.
     // records addressed by a byte offset, so that every row load is one
     // immediate offset from the same register
 #define REC_AT(off) (reinterpret_cast<const char*>(t_rec) + (off))
