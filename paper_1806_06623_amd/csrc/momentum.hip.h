@@ -393,6 +393,10 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
     // r-face i0 - 1/2 (tangential parts the means of cells i0 - 1 and i0,
     // cell i0's alone at the inner face)
     double prev[3], cur[3], nxt[3], grl[3];
+    // theta and phi components of the current row (and its face quotients),
+    // computed once: as the next row's while the row below forms its upper
+    // r-face, then carried into that row's own iteration
+    double o_ct, o_cp, o_gtl, o_gth, o_gpl, o_gph;
     column(i0 - 1, prev);
     column(i0, cur);
     column(i0 + 1, nxt);
@@ -404,11 +408,11 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
         const double f = t.invdr[i0];   // 0 at the inner face
 #pragma unroll
         for (int a = 0; a < 3; ++a) grl[a] = (cur[a] - prev[a]) * f;
-        double ct0, cp0, x0, x1, x2, x3;
-        own_tp(i0, t.invr[i0], cur, ct0, cp0, x0, x1, x2, x3);
+        own_tp(i0, t.invr[i0], cur, o_ct, o_cp, o_gtl, o_gth, o_gpl, o_gph);
+        const double ct0 = o_ct, cp0 = o_cp;
         double g1 = ct0, g2 = cp0;
         if (i0 > 0) {
-            double ctb, cpb;
+            double ctb, cpb, x0, x1, x2, x3;
             own_tp(i0 - 1, t.invr[i0 - 1], prev, ctb, cpb, x0, x1, x2, x3);
             g1 = avg(ctb, ct0);
             g2 = avg(cpb, cp0);
@@ -431,9 +435,9 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
         rquot(i, srow[1][r], cur, nxt, grh);
 #pragma unroll
         for (int a = 0; a < 3; ++a) cr[a] = avg(grl[a], grh[a]);
-        double ct, gtl, gth, gpl, gph;
+        const double ct = o_ct, gtl = o_gtl, gth = o_gth, gph = o_gph;
+        cp[1] = o_cp;
         const double ir = srow[0][r];
-        own_tp(i, ir, cur, ct, cp[1], gtl, gth, gpl, gph);
 #pragma unroll
         for (int a = 0; a < 3; a += 2) {
             const double rp = ir * qp[a];
@@ -458,10 +462,9 @@ __global__ __launch_bounds__(THREADS) void k_momentum_rows(const double* __restr
         // (its Phi published above), or the cell's own at the outer face
         double g1 = ct, g2 = cp[1];
         if (i + 1 < nr) {
-            double ctn, cpn, x0, x1, x2, x3;
-            own_tp(i + 1, srow[0][r + 1], nxt, ctn, cpn, x0, x1, x2, x3);
-            g1 = avg(ct, ctn);
-            g2 = avg(cp[1], cpn);
+            own_tp(i + 1, srow[0][r + 1], nxt, o_ct, o_cp, o_gtl, o_gth, o_gpl, o_gph);
+            g1 = avg(ct, o_ct);
+            g2 = avg(cp[1], o_cp);
         }
         const double srr = k4 * srow[3][r];
         const V3 upr = rvec(scalars(grh[1], g1, g2, srr, 0.5 * srr), S2, SC, SN, jck, jsk, dphi);
