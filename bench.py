@@ -81,13 +81,13 @@ TRAFFIC = {
     "modal::k_modal": {"grid": (550, 128, 256),
                        "sources": ("modal.hip.h", "modal_layout.h", "radial.hip.h", "status.h", "solve.hip"),
                        "source_digest": "9387555aa5f1cb12",
-                       "bytes_per_launch": (81339.5 * 2.0 + 140806.0) * 1024.0},
+                       "bytes_per_launch": (81339.4 * 2.0 + 140806.0) * 1024.0},
     "faceflux::k_face_fluxes": {"grid": (550, 128, 256), "sources": ("fluxes.hip.h", "xcd.h", "solve.hip"),
                                 "source_digest": "b2a25584f1ab1bc0",
                                 "bytes_per_launch": (74482.1 * 2.0 + 422617.4) * 1024.0},
     "momentum::k_momentum_rows": {"grid": (550, 128, 256), "sources": ("momentum.hip.h", "xcd.h", "solve.hip"),
-                                  "source_digest": "14a8e28ce87a9ca8",
-                                  "bytes_per_launch": (78511.6 * 2.0 + 422400.1) * 1024.0},
+                                  "source_digest": "b3a35a7931e3d9f5",
+                                  "bytes_per_launch": (78505.7 * 2.0 + 422400.2) * 1024.0},
     "k_residual_rows": {"grid": (550, 128, 256), "sources": ("solve.hip", "internal.h", "xcd.h", "status.h"),
                         "source_digest": "3175b7ca1d3e8f72",
                         "bytes_per_launch": (148724.0 * 2.0 + 140800.0) * 1024.0},
